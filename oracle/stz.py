@@ -1,0 +1,110 @@
+"""Athermal STZ plasticity and the quasi-static projection step.
+
+Paper Sec. 3.1 (plastic rate of deformation, effective temperature) and
+Sec. 3.3 (intermediate stress, projection, stress correction), written in the
+nondimensional units of `workloads.stz_constants` (stress in E, time in t_s,
+length in L, chi in e_z/k_B).
+
+Readings where the paper is silent or inconsistent (also in the design notes):
+  * the objective-rate term is -tr(L) sigma, as in the definition of the
+    Truesdell rate (Sec. 2.1) and Eq. sig_star_qs;
+  * D^pl = 0 when sbar <= s_Y (the factor 1 - s_Y/sbar would be negative);
+  * the effective temperature takes a forward-Euler step with the state at
+    step n; the diffusion term of Eq. chi_evo is not included (l = 0);
+  * Eq. sig_star_qs has no advection term, so none is applied.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .operators import (div_node, full_to_voigt, grad_cell, stiffness, sym,
+                        voigt_to_full)
+
+
+def transition_rate(sbar, p):
+    """C(sbar, T) = exp(-Delta/kT) cosh(Omega eps0 sbar / kT) (Eq. stz_C_form)."""
+    return np.exp(-p["delta_over_T"]) * np.cosh(p["beta"] * sbar)
+
+
+def transition_rate_from_R(sbar, p):
+    """C = (R(+sbar) + R(-sbar)) / 2 with the stress-biased rates of Eq. stz_R."""
+    Rp = np.exp(-p["delta_over_T"] + p["beta"] * sbar)
+    Rm = np.exp(-p["delta_over_T"] - p["beta"] * sbar)
+    return 0.5 * (Rp + Rm)
+
+
+def deviator(S):
+    """sigma_0 = sigma - tr(sigma)/3 I and sbar = sqrt(sum sigma_0,ij^2 / 2)."""
+    p = (S[0, 0] + S[1, 1] + S[2, 2]) / 3.0
+    S0 = S.copy()
+    for a in range(3):
+        S0[a, a] = S0[a, a] - p
+    sbar = np.sqrt(0.5 * np.sum(S0 * S0, axis=(0, 1)))
+    return S0, sbar
+
+
+def plastic_rate(sbar, chi, p):
+    """Scalar D^pl of Eq. stz_dpl; zero at or below the yield stress."""
+    out = np.zeros(np.broadcast(sbar, chi).shape)
+    act = sbar > p["s_y"]
+    sb = np.where(act, sbar, p["s_y"])
+    val = (np.exp(-1.0 / chi) * transition_rate(sb, p) * (1.0 - p["s_y"] / sb) / p["tau0"])
+    out[...] = np.where(act, val, 0.0)
+    return out
+
+
+def stz_step(v, sigma, chi, h, dt, lam, mu, p):
+    """Intermediate stress (Eq. sig_star_qs) and the updated chi (Eq. chi_evo).
+
+    v: node velocity at step n (walls included), sigma: Voigt cell stress,
+    chi: cell effective temperature.  Returns (sigma_star, chi_next).
+    """
+    L = grad_cell(v, h)
+    S = voigt_to_full(sigma)
+    S0, sbar = deviator(S)
+    Dpl = plastic_rate(sbar, chi, p)
+    safe = np.where(sbar > 0.0, sbar, 1.0)
+    ratio = np.where(Dpl > 0.0, Dpl / safe, 0.0)
+    trL = L[0, 0] + L[1, 1] + L[2, 2]
+    LS = np.einsum("ab...,bc...->ac...", L, S)
+    SLt = np.einsum("ab...,cb...->ac...", S, L)
+    plastic = stiffness(ratio * S0, lam, mu)
+    Sstar = S + dt * (LS + SLt - trL * S - plastic)
+    # D^pl (tensor) : sigma_0 = (D^pl / sbar) sigma_0 : sigma_0 = 2 sbar D^pl
+    chi_next = chi + (dt / p["c0"]) * (2.0 * sbar * Dpl / p["s_y"]) * (p["chi_inf"] - chi)
+    return full_to_voigt(Sstar), chi_next
+
+
+def rhs(sigma_star, h, dt):
+    """b = D_h sigma* / dt at the interior nodes (Eq. proj, sign flipped)."""
+    return div_node(sigma_star, h) / dt
+
+
+def stress_update(sigma_star, v, h, dt, lam, mu):
+    """sigma^{n+1} = sigma* + dt C : D^{n+1}, D = sym(G_h v^{n+1}) (Eq. sig_n+1)."""
+    D = sym(grad_cell(v, h))
+    return sigma_star + dt * full_to_voigt(stiffness(D, lam, mu))
+
+
+def set_shear_walls(v, U):
+    """Wall velocities of Eq. u_bc: (-U, 0, 0) at k = 0 and (+U, 0, 0) at k = nz."""
+    v = v.copy()
+    v[:, 0] = 0.0
+    v[:, -1] = 0.0
+    v[0, 0] = -U
+    v[0, -1] = U
+    return v
+
+
+def projection_step(v, sigma, chi, h, dt, lam, mu, p, U, solver, rtol=1e-10, max_cycles=100):
+    """One quasi-static step n -> n+1 (Sec. 3.3).
+
+    `solver` is an oracle multigrid (`MGOracle`) for the same grid; the solve
+    is warm-started from v^n with the new wall values.
+    """
+    sstar, chi_next = stz_step(v, sigma, chi, h, dt, lam, mu, p)
+    b = rhs(sstar, h, dt)
+    x0 = set_shear_walls(v, U)
+    v_next, info = solver.solve(b, x0, rtol=rtol, max_cycles=max_cycles)
+    s_next = stress_update(sstar, v_next, h, dt, lam, mu)
+    return v_next, s_next, chi_next, info

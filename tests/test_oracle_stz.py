@@ -1,0 +1,142 @@
+"""Pins of the oracle STZ update and projection step (paper Secs. 3.1 and 3.3)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import stz
+from oracle.multigrid import MGOracle
+from oracle.operators import voigt_to_full
+from workloads import chi_field, lame, shear_velocity, stz_constants
+
+LAM, MU = lame()
+P = stz_constants()
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_table1_conversion_matches_printed_values():
+    """Derived quantities printed in the paper: mu = 37.4 GPa, c_s = 2.47 km/s,
+    t_s = L/c_s = 4.05 us (Table 1 and Sec. 4)."""
+    g = json.load(open(os.path.join(GOLDEN, "table1.json")))
+    E = g["E_GPa"] * 1e9
+    mu = E / (2 * (1 + g["nu"]))
+    assert round(mu / 1e9, 1) == g["mu_GPa_printed"]
+    cs = math.sqrt(mu / g["rho_kg_m3"])
+    assert round(cs / 1e3, 2) == g["c_s_km_s_printed"]
+    assert round(0.01 / cs * 1e6, 2) == g["t_s_us_printed"]
+    assert P["tau0"] == pytest.approx(g["tau0_s"] / (0.01 / cs), rel=1e-12)
+    assert P["s_y"] == pytest.approx(0.85 / 101, rel=1e-12)
+    assert P["chi_inf"] == pytest.approx(900 / 21000, rel=1e-12)
+    assert P["delta_over_T"] == 20.0
+
+
+def test_transition_rate_identity():
+    """C = (R(+s) + R(-s))/2 = exp(-Delta/kT) cosh(Omega eps0 s/kT) (Eqs. stz_R, stz_C_form)."""
+    s = np.linspace(0.0, 0.02, 101)
+    a = stz.transition_rate(s, P)
+    b = stz.transition_rate_from_R(s, P)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+
+
+def test_deviator_and_yield():
+    rng = np.random.default_rng(0)
+    sig = rng.standard_normal((6, 2, 3, 4)) * 0.01
+    S0, sbar = stz.deviator(voigt_to_full(sig))
+    assert np.abs(S0[0, 0] + S0[1, 1] + S0[2, 2]).max() < 1e-16
+    # pure shear: sbar = |sigma_xz|
+    pure = np.zeros((6, 1, 1, 1))
+    pure[4] = -0.0123
+    _, sb = stz.deviator(voigt_to_full(pure))
+    assert sb.item() == pytest.approx(0.0123, rel=1e-15)
+    # no plastic flow at or below yield
+    assert np.all(stz.plastic_rate(np.array([0.0, P["s_y"] * 0.999, P["s_y"]]), 0.05, P) == 0.0)
+    assert stz.plastic_rate(np.array([P["s_y"] * 1.01]), 0.05, P)[0] > 0.0
+
+
+def _uniform(nz, vals):
+    s = np.zeros((6, nz, nz, nz))
+    for n, v in enumerate(vals):
+        s[n] = v
+    return s
+
+
+def test_plastic_relaxation_closed_form():
+    """With L = 0 the update only shrinks the deviator: sbar* = sbar - 2 mu dt D^pl,
+    pressure and deviator direction unchanged; chi moves toward chi_inf."""
+    n, dt = 4, 3.0
+    rng = np.random.default_rng(1)
+    vals = rng.standard_normal(6) * 0.006
+    sig = _uniform(n, vals)
+    chi = np.full((n, n, n), 0.05)
+    v = np.zeros((3, n + 1, n, n))
+    S = voigt_to_full(sig)
+    S0, sbar = stz.deviator(S)
+    Dpl = stz.plastic_rate(sbar, chi, P)
+    assert np.all(Dpl > 0)
+    sstar, chi1 = stz.stz_step(v, sig, chi, 1.0 / n, dt, LAM, MU, P)
+    T = voigt_to_full(sstar)
+    T0, tbar = stz.deviator(T)
+    assert np.abs(tbar - (sbar - 2 * MU * dt * Dpl)).max() < 1e-15
+    assert np.abs(np.trace(T) - np.trace(S)).max() < 1e-16
+    assert np.abs(T0 / tbar - S0 / sbar).max() < 1e-12
+    assert np.all(chi1 < chi) and np.all(chi1 > P["chi_inf"])
+
+
+def test_truesdell_kinematics_closed_form():
+    """Below yield: simple shear v_x = g z acting on sigma_zz = s gives
+    sigma*_xz = dt g s (L sigma + sigma L^T); a dilatation L = e I scales an
+    isotropic stress by 1 - dt e (2 - 3)."""
+    n, dt, g, s = 4, 0.5, 1e-3, 2e-3
+    h = 1.0 / n
+    sig = _uniform(n, [0, 0, s, 0, 0, 0])
+    chi = np.full((n, n, n), 0.05)
+    v = shear_velocity(n, n, n, g / 2.0)  # v_x = (g/2)(2z - 1), so dv_x/dz = g
+    sstar, chi1 = stz.stz_step(v, sig, chi, h, dt, LAM, MU, P)
+    expect = sig.copy()
+    expect[4] += dt * g * s
+    assert np.abs(sstar - expect).max() < 1e-17
+    assert np.array_equal(chi1, chi)
+    # pure dilatation in z only is the one linear field allowed with periodic x, y:
+    # L = diag(0, 0, e): sigma = p I -> sigma* = p I + dt (2 e p e_z e_z - e p I)
+    e, p = 2e-3, 1e-3
+    v = np.zeros((3, n + 1, n, n))
+    v[2] = (e * np.arange(n + 1) * h)[:, None, None]
+    sig = _uniform(n, [p, p, p, 0, 0, 0])
+    sstar, _ = stz.stz_step(v, sig, chi, h, dt, LAM, MU, P)
+    want = np.array([p - dt * e * p, p - dt * e * p, p + dt * (2 * e * p - e * p), 0, 0, 0])
+    assert np.abs(sstar - want[:, None, None, None]).max() < 1e-18
+
+
+def test_homogeneous_shear_step_reduces_to_scalar_recursion():
+    """Uniform chi and sigma with a linear wall-to-wall velocity: the step keeps
+    the linear profile (0 cycles from a warm start) and a uniform stress that
+    follows the one-cell update plus dt * 2 mu * U of elastic loading."""
+    n, dt, U = 8, 10.0, 1e-5
+    h = 1.0 / n
+    mg = MGOracle(n, n, n, h, LAM, MU)
+    sig = _uniform(n, [0, 0, 0, 0, 1.01 * P["s_y"], 0])
+    chi = np.full((n, n, n), 0.05)
+    v = shear_velocity(n, n, n, U)
+    v1, s1, chi1, info = stz.projection_step(v, sig, chi, h, dt, LAM, MU, P, U, mg)
+    assert info["cycles"] == 0
+    assert np.abs(v1 - v).max() == 0.0
+    # one-cell evaluation of the same step
+    one = stz.stz_step(shear_velocity(1, 1, 1, U), sig[:, :1, :1, :1], chi[:1, :1, :1],
+                       1.0, dt, LAM, MU, P)[0]
+    # sym(grad v)_xz = U (dv_x/dz = 2U), C : D adds 2 mu U to sigma_xz
+    expect = one[:, 0, 0, 0].copy()
+    expect[4] += dt * 2 * MU * U
+    assert np.abs(s1 - expect[:, None, None, None]).max() < 1e-18
+    # from a zero initial guess the solve converges to the same profile
+    v0 = stz.set_shear_walls(np.zeros_like(v), U)
+    x, info = mg.solve(np.zeros_like(v), v0, rtol=1e-12)
+    assert np.abs(x - v).max() < 1e-11 * U
+
+
+def test_chi_field_statistics():
+    """Eq. convolve keeps the pointwise mean and std of the random field."""
+    chi = chi_field(96, 96, 96, seed=3, mean=0.05, std=0.003, lc_cells=4.0)
+    assert abs(chi.mean() - 0.05) < 2e-4
+    assert abs(chi.std() / 0.003 - 1.0) < 0.08
