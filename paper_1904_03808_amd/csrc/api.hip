@@ -1,0 +1,638 @@
+// C ABI of libqsmg: handle, workspace layout, V-cycle drivers and the solve
+// loops (paper Sec. 3.6), plus the projection step of Sec. 3.3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "device.h"
+#include "hierarchy.h"
+#include "qsmg.h"
+
+using namespace qs;
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+
+struct LevelBufs {
+  Dims d{0, 0, 0};
+  double* x64 = nullptr;
+  double* b64 = nullptr;
+  double* r64 = nullptr;
+  float* x32 = nullptr;
+  float* b32 = nullptr;
+  float* r32 = nullptr;
+  double* S64 = nullptr;
+  double* D64 = nullptr;
+  float* S32 = nullptr;
+  float* D32 = nullptr;
+};
+
+// Assigns aligned sub-buffers of the workspace; with base == nullptr it only
+// measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~static_cast<size_t>(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+bool valid_params(const qs_params* p) {
+  if (!p) return false;
+  if (p->precision != QS_FP64 && p->precision != QS_FP32_IR) return false;
+  if (p->n_pre < 0 || p->n_post < 0 || p->n_pre > 16 || p->n_post > 16) return false;
+  if (!(p->h > 0.0) || !(p->mu > 0.0) || !(p->lambda + p->mu > 0.0)) return false;
+  int seen = 0;
+  for (int q = 0; q < 8; ++q) {
+    const int c = p->colour_order[q];
+    if (c < 0 || c > 7 || (seen >> c) & 1) return false;
+    seen |= 1 << c;
+  }
+  return true;
+}
+
+int plan(const qs_params* p, std::vector<int>* dims) {
+  if (plan_levels(p->nx, p->ny, p->nz, p->min_coarse_nz, dims) != 0) return -2;
+  // 32-bit element indexing inside the kernels
+  const long long elems = 3LL * (p->nz + 1) * p->ny * p->nx;
+  if (elems >= (1LL << 31) || static_cast<int>(dims->size() / 3) > kMaxLevels) return -2;
+  return 0;
+}
+
+}  // namespace
+
+struct qs_handle {
+  qs_params p;
+  hipStream_t stream = nullptr;
+  int nlev = 0;
+  LevelBufs L[kMaxLevels];
+  FineCoef<double> fc64;
+  FineCoef<float> fc32;
+  double* Ainv = nullptr;
+  int ncoarse = 0;
+  double* ctin = nullptr;
+  double* ctout = nullptr;
+  double* partial = nullptr;
+  int partial_n = 0;
+  double* dnorm = nullptr;   // device, 4 doubles
+  double* pinned = nullptr;  // host pinned, 4 doubles
+};
+
+namespace {
+
+void carve(const qs_params* p, const std::vector<int>& dims, char* base, qs_handle* hd,
+           size_t* total) {
+  Carver cv{base};
+  const int nlev = static_cast<int>(dims.size() / 3);
+  int maxblocks = 1;
+  for (int l = 0; l < nlev; ++l) {
+    LevelBufs lb;
+    lb.d = Dims{dims[3 * l], dims[3 * l + 1], dims[3 * l + 2]};
+    const size_t e = lb.d.elems();
+    if (p->precision == QS_FP64) {
+      if (l > 0) {
+        lb.x64 = cv.take<double>(e);
+        lb.b64 = cv.take<double>(e);
+      }
+      lb.r64 = cv.take<double>(e);
+    } else {
+      lb.x32 = cv.take<float>(e);
+      lb.b32 = cv.take<float>(e);
+      if (l < nlev - 1) lb.r32 = cv.take<float>(e);
+    }
+    const size_t planes = static_cast<size_t>(lb.d.nz + 1);
+    lb.S64 = cv.take<double>(planes * kStencil);
+    lb.D64 = cv.take<double>(planes * 9);
+    lb.S32 = cv.take<float>(planes * kStencil);
+    lb.D32 = cv.take<float>(planes * 9);
+    const int nb = residual_blocks(lb.d);
+    if (nb > maxblocks) maxblocks = nb;
+    if (hd) hd->L[l] = lb;
+  }
+  const Dims g{dims[3 * (nlev - 1)], dims[3 * (nlev - 1) + 1], dims[3 * (nlev - 1) + 2]};
+  const int nc = 3 * g.nx * g.ny * (g.nz - 1);
+  double* Ainv = cv.take<double>(static_cast<size_t>(nc) * nc);
+  double* ctin = cv.take<double>(nc);
+  double* ctout = cv.take<double>(nc);
+  double* partial = cv.take<double>(maxblocks);
+  double* dnorm = cv.take<double>(4);
+  if (hd) {
+    hd->nlev = nlev;
+    hd->ncoarse = nc;
+    hd->Ainv = Ainv;
+    hd->ctin = ctin;
+    hd->ctout = ctout;
+    hd->partial = partial;
+    hd->partial_n = maxblocks;
+    hd->dnorm = dnorm;
+  }
+  *total = (cv.off + 255) & ~static_cast<size_t>(255);
+}
+
+#define QS_HIP(call)                              \
+  do {                                            \
+    if ((call) != hipSuccess) return QS_ERR_HIP;  \
+  } while (0)
+
+qs_status launch_check() {
+  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+}
+
+// Read the reduced double written to hd->dnorm[0].
+qs_status read_norm(qs_handle* hd, double* out) {
+  QS_HIP(hipGetLastError());
+  QS_HIP(hipMemcpyAsync(hd->pinned, hd->dnorm, sizeof(double), hipMemcpyDeviceToHost, hd->stream));
+  QS_HIP(hipStreamSynchronize(hd->stream));
+  *out = hd->pinned[0];
+  return QS_OK;
+}
+
+// ---- level operations in working precision T ----------------------------
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static double* x(LevelBufs& l) { return l.x64; }
+  static double* b(LevelBufs& l) { return l.b64; }
+  static double* r(LevelBufs& l) { return l.r64; }
+  static const double* S(LevelBufs& l) { return l.S64; }
+  static const double* D(LevelBufs& l) { return l.D64; }
+  static const FineCoef<double>& fc(qs_handle* hd) { return hd->fc64; }
+};
+template <>
+struct Prec<float> {
+  static float* x(LevelBufs& l) { return l.x32; }
+  static float* b(LevelBufs& l) { return l.b32; }
+  static float* r(LevelBufs& l) { return l.r32; }
+  static const float* S(LevelBufs& l) { return l.S32; }
+  static const float* D(LevelBufs& l) { return l.D32; }
+  static const FineCoef<float>& fc(qs_handle* hd) { return hd->fc32; }
+};
+
+template <typename T>
+void colour_pass(qs_handle* hd, int l, T* x, const T* b, int colour) {
+  LevelBufs& lb = hd->L[l];
+  if (l == 0)
+    launch_colour_fine<T>(x, b, lb.d, colour, Prec<T>::fc(hd), hd->stream);
+  else
+    launch_colour_gen<T>(x, b, lb.d, colour, Prec<T>::S(lb), Prec<T>::D(lb), hd->stream);
+}
+
+template <typename T>
+void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_interior) {
+  LevelBufs& lb = hd->L[l];
+  if (l == 0)
+    launch_residual_fine<T, T>(x, b, r, lb.d, hd->fc64, 1.0, zero_interior, nullptr, hd->stream);
+  else
+    launch_residual_gen<T>(x, b, r, lb.d, Prec<T>::S(lb), zero_interior, nullptr, hd->stream);
+}
+
+// Coarsest level: x_interior = A^{-1} (b - A_IB x_B).  Only the FP64 fine
+// level carries wall data; coarse levels and the FP32 correction equation
+// have zero walls, and b is used directly.
+template <typename T>
+void coarse_solve(qs_handle* hd, int l, T* x, const T* b, T* scratch) {
+  LevelBufs& lb = hd->L[l];
+  const T* rhs = b;
+  if (l == 0 && sizeof(T) == sizeof(double)) {
+    residual<T>(hd, l, x, b, scratch, true);
+    rhs = scratch;
+  }
+  launch_coarse_solve<T>(hd->Ainv, hd->ncoarse, rhs, x, lb.d, hd->ctin, hd->ctout, hd->stream);
+}
+
+template <typename T>
+void vcycle(qs_handle* hd, int l, T* x, const T* b) {
+  LevelBufs& lb = hd->L[l];
+  if (l == hd->nlev - 1) {
+    coarse_solve<T>(hd, l, x, b, Prec<T>::r(lb));
+    return;
+  }
+  const int* ord = hd->p.colour_order;
+  for (int s = 0; s < hd->p.n_pre; ++s)
+    for (int q = 0; q < 8; ++q) colour_pass<T>(hd, l, x, b, ord[q]);
+  LevelBufs& cb = hd->L[l + 1];
+  T* r = Prec<T>::r(lb);
+  residual<T>(hd, l, x, b, r, false);
+  launch_restrict<T>(r, Prec<T>::b(cb), lb.d, hd->stream);
+  launch_fill<T>(Prec<T>::x(cb), cb.d.elems(), T(0), hd->stream);
+  vcycle<T>(hd, l + 1, Prec<T>::x(cb), Prec<T>::b(cb));
+  launch_prolong_add<T>(x, Prec<T>::x(cb), lb.d, hd->stream);
+  for (int s = 0; s < hd->p.n_post; ++s)
+    for (int q = 7; q >= 0; --q) colour_pass<T>(hd, l, x, b, ord[q]);
+}
+
+// ||b - K x||^2 on level 0 in FP64 (optionally writing the residual, scaled,
+// in FP32 for the refinement loop); result in hd->dnorm[0].
+template <typename Tout>
+int residual_norm0(qs_handle* hd, const double* x, const double* b, Tout* r, double scale,
+                   bool zero_interior) {
+  const int nb = launch_residual_fine<double, Tout>(x, b, r, hd->L[0].d, hd->fc64, scale,
+                                                    zero_interior, hd->partial, hd->stream);
+  launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->stream);
+  return nb;
+}
+
+double pow2_near(double v) {
+  if (!(v > 0.0) || !std::isfinite(v)) return 1.0;
+  return std::ldexp(1.0, static_cast<int>(std::lround(std::log2(v))));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qs_status_string(int s) {
+  switch (s) {
+    case QS_OK: return "ok";
+    case QS_ERR_ARG: return "invalid argument";
+    case QS_ERR_SHAPE: return "grid shape not supported";
+    case QS_ERR_HIP: return "HIP runtime error";
+    case QS_ERR_NOT_CONVERGED: return "not converged";
+    case QS_ERR_NONFINITE: return "non-finite residual";
+    case QS_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    default: return "unknown status";
+  }
+}
+
+qs_status qs_workspace_bytes(const qs_params* p, size_t* bytes) {
+  if (!valid_params(p) || !bytes) return QS_ERR_ARG;
+  std::vector<int> dims;
+  if (plan(p, &dims) != 0) return QS_ERR_SHAPE;
+  carve(p, dims, nullptr, nullptr, bytes);
+  return QS_OK;
+}
+
+qs_status qs_level_dims(const qs_params* p, int level, int* nlev, int* nx, int* ny, int* nz) {
+  if (!valid_params(p)) return QS_ERR_ARG;
+  std::vector<int> dims;
+  if (plan(p, &dims) != 0) return QS_ERR_SHAPE;
+  const int n = static_cast<int>(dims.size() / 3);
+  if (nlev) *nlev = n;
+  if (level < 0 || level >= n) return QS_ERR_ARG;
+  if (nx) *nx = dims[3 * level];
+  if (ny) *ny = dims[3 * level + 1];
+  if (nz) *nz = dims[3 * level + 2];
+  return QS_OK;
+}
+
+qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, void* stream,
+                   qs_handle** out) {
+  if (!valid_params(p) || !out) return QS_ERR_ARG;
+  *out = nullptr;
+  std::vector<int> dims;
+  if (plan(p, &dims) != 0) return QS_ERR_SHAPE;
+  size_t need = 0;
+  carve(p, dims, nullptr, nullptr, &need);
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) || workspace_bytes < need)
+    return QS_ERR_WORKSPACE;
+  HostHierarchy H;
+  if (build_hierarchy(p->nx, p->ny, p->nz, p->h, p->lambda, p->mu, p->min_coarse_nz, &H) != 0)
+    return QS_ERR_SHAPE;
+  qs_handle* hd = new (std::nothrow) qs_handle();
+  if (!hd) return QS_ERR_ARG;
+  hd->p = *p;
+  hd->stream = static_cast<hipStream_t>(stream);
+  carve(p, dims, static_cast<char*>(workspace), hd, &need);
+  if (hipHostMalloc(reinterpret_cast<void**>(&hd->pinned), 4 * sizeof(double)) != hipSuccess) {
+    delete hd;
+    return QS_ERR_HIP;
+  }
+  const double lam = p->lambda, mu = p->mu, h = p->h;
+  hd->fc64.h2 = h * h;
+  hd->fc64.p = lam + 2.0 * mu;
+  hd->fc64.q = mu;
+  hd->fc64.m4 = 0.25 * (lam + mu);
+  hd->fc64.inv_diag = 1.0 / (2.0 * (lam + 4.0 * mu));
+  hd->fc64.ih2 = 1.0 / (h * h);
+  hd->fc32.h2 = static_cast<float>(hd->fc64.h2);
+  hd->fc32.p = static_cast<float>(hd->fc64.p);
+  hd->fc32.q = static_cast<float>(hd->fc64.q);
+  hd->fc32.m4 = static_cast<float>(hd->fc64.m4);
+  hd->fc32.inv_diag = static_cast<float>(hd->fc64.inv_diag);
+  hd->fc32.ih2 = static_cast<float>(hd->fc64.ih2);
+  // upload stencils (FP64 and their FP32 roundings) and the coarse inverse;
+  // the staging vectors live until the synchronisation below
+  std::vector<std::vector<float>> stage32;
+  stage32.reserve(2 * hd->nlev);
+  qs_status st = QS_OK;
+  for (int l = 0; l < hd->nlev && st == QS_OK; ++l) {
+    const HostLevel& hl = H.levels[l];
+    LevelBufs& lb = hd->L[l];
+    stage32.emplace_back(hl.stencil.begin(), hl.stencil.end());
+    const std::vector<float>& s32 = stage32.back();
+    stage32.emplace_back(hl.dinv.begin(), hl.dinv.end());
+    const std::vector<float>& d32 = stage32.back();
+    if (hipMemcpyAsync(lb.S64, hl.stencil.data(), hl.stencil.size() * 8, hipMemcpyHostToDevice,
+                       hd->stream) != hipSuccess ||
+        hipMemcpyAsync(lb.D64, hl.dinv.data(), hl.dinv.size() * 8, hipMemcpyHostToDevice,
+                       hd->stream) != hipSuccess ||
+        hipMemcpyAsync(lb.S32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, hd->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(lb.D32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice, hd->stream) !=
+            hipSuccess)
+      st = QS_ERR_HIP;
+  }
+  if (st == QS_OK && hipMemcpyAsync(hd->Ainv, H.coarse_inv.data(), H.coarse_inv.size() * 8,
+                                    hipMemcpyHostToDevice, hd->stream) != hipSuccess)
+    st = QS_ERR_HIP;
+  if (hipStreamSynchronize(hd->stream) != hipSuccess) st = QS_ERR_HIP;
+  if (st != QS_OK) {
+    (void)hipHostFree(hd->pinned);
+    delete hd;
+    return st;
+  }
+  *out = hd;
+  return QS_OK;
+}
+
+qs_status qs_destroy(qs_handle* hd) {
+  if (!hd) return QS_ERR_ARG;
+  if (hd->pinned) (void)hipHostFree(hd->pinned);
+  delete hd;
+  return QS_OK;
+}
+
+qs_status qs_apply(qs_handle* hd, const double* x, double* y) {
+  if (!hd || !x || !y || x == y) return QS_ERR_ARG;
+  const Dims d = hd->L[0].d;
+  // y = -(0 - K x) on the interior, walls zeroed
+  launch_residual_fine<double, double>(x, nullptr, y, d, hd->fc64, -1.0, false, nullptr,
+                                       hd->stream);
+  for (int c = 0; c < 3; ++c) {
+    launch_fill<double>(y + static_cast<size_t>(c) * d.comp(), d.plane(), 0.0, hd->stream);
+    launch_fill<double>(y + static_cast<size_t>(c) * d.comp() + static_cast<size_t>(d.nz) * d.plane(),
+                        d.plane(), 0.0, hd->stream);
+  }
+  return launch_check();
+}
+
+static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rtol, int max_cycles,
+                            qs_solve_info* info) {
+  const Dims d0 = hd->L[0].d;
+  const double nunk = 3.0 * d0.nx * d0.ny * (d0.nz - 1);
+  qs_solve_info local;
+  qs_solve_info* inf = info ? info : &local;
+  std::memset(inf, 0, sizeof(*inf));
+  inf->levels = hd->nlev;
+  double nb2 = 0.0;
+  residual_norm0<double>(hd, x, b, nullptr, 1.0, true);
+  qs_status st = read_norm(hd, &nb2);
+  if (st != QS_OK) return st;
+  if (!std::isfinite(nb2)) return QS_ERR_NONFINITE;
+  if (nb2 == 0.0) {
+    launch_zero_interior<double>(x, d0, hd->stream);
+    inf->rel_res = 0.0;
+    inf->rel_res_hist[0] = 0.0;
+    return launch_check();
+  }
+  const bool fixed = !(rtol > 0.0);
+  const bool ir = hd->p.precision == QS_FP32_IR;
+  double scale = pow2_near(std::sqrt(nb2 / nunk));
+  double scale_used = scale;
+  int cycles = 0;
+  double rel = 0.0;
+  for (;;) {
+    const bool need_norm = !fixed || cycles == max_cycles;
+    if (ir) {
+      // FP64 residual, written as FP32 scaled by 1/scale for the inner cycle
+      scale_used = scale;
+      residual_norm0<float>(hd, x, b, hd->L[0].b32, 1.0 / scale_used, false);
+    } else if (need_norm) {
+      residual_norm0<double>(hd, x, b, nullptr, 1.0, false);
+    }
+    if (need_norm) {
+      double rn2 = 0.0;
+      st = read_norm(hd, &rn2);
+      if (st != QS_OK) return st;
+      rel = std::sqrt(rn2 / nb2);
+      if (cycles < QS_HIST) inf->rel_res_hist[cycles] = rel;
+      inf->rel_res = rel;
+      if (!std::isfinite(rel)) {
+        inf->cycles = cycles;
+        return QS_ERR_NONFINITE;
+      }
+      if (!fixed && rel <= rtol) break;
+      if (ir) scale = pow2_near(std::sqrt(rn2 / nunk));
+    }
+    if (cycles == max_cycles) {
+      inf->cycles = cycles;
+      return fixed ? QS_OK : QS_ERR_NOT_CONVERGED;
+    }
+    if (ir) {
+      // correction e solves A e = r / scale_used in FP32; x += scale_used e
+      LevelBufs& l0 = hd->L[0];
+      launch_fill<float>(l0.x32, l0.d.elems(), 0.0f, hd->stream);
+      vcycle<float>(hd, 0, l0.x32, l0.b32);
+      launch_ir_update(x, l0.x32, d0, scale_used, hd->stream);
+    } else {
+      vcycle<double>(hd, 0, x, b);
+    }
+    ++cycles;
+  }
+  inf->cycles = cycles;
+  return launch_check();
+}
+
+qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol, int max_cycles,
+                      qs_solve_info* info) {
+  if (!hd || !b || !x || max_cycles < 0 || b == x) return QS_ERR_ARG;
+  return solve_impl(hd, b, x, rtol, max_cycles, info);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// STZ step, projection step and their reverse-mode pieces (Secs. 3.1, 3.3)
+// ---------------------------------------------------------------------------
+namespace {
+
+bool valid_stz(const qs_stz_params* sp) {
+  return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt);
+}
+
+StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
+  StzArgs a;
+  a.s_y = sp->s_y;
+  a.tau0 = sp->tau0;
+  a.beta = sp->beta;
+  a.delta_over_T = sp->delta_over_T;
+  a.c0 = sp->c0;
+  a.chi_inf = sp->chi_inf;
+  a.dt = sp->dt;
+  a.lam = hd->p.lambda;
+  a.mu = hd->p.mu;
+  a.h = hd->p.h;
+  return a;
+}
+
+size_t cells(const Dims& d) { return static_cast<size_t>(d.nx) * d.ny * d.nz; }
+
+size_t step_scratch(qs_handle* hd) {
+  const Dims d = hd->L[0].d;
+  const size_t a = (7 * cells(d) + d.elems()) * sizeof(double) + 512;
+  const size_t b = 9 * cells(d) * sizeof(double) + 256;
+  return a > b ? a : b;
+}
+
+}  // namespace
+
+extern "C" {
+
+qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v, const double* sigma,
+                      const double* chi, double* sigma_star, double* chi_next) {
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !sigma_star || !chi_next) return QS_ERR_ARG;
+  if (sigma_star == sigma || chi_next == chi) return QS_ERR_ARG;
+  launch_stz_step(v, sigma, chi, sigma_star, chi_next, hd->L[0].d, stz_args(hd, sp), hd->stream);
+  return launch_check();
+}
+
+qs_status qs_rhs(qs_handle* hd, const double* sigma_star, double dt, double* b) {
+  if (!hd || !sigma_star || !b || !(dt != 0.0)) return QS_ERR_ARG;
+  launch_rhs(sigma_star, b, hd->L[0].d, hd->p.h, dt, hd->stream);
+  return launch_check();
+}
+
+qs_status qs_stress_update(qs_handle* hd, const double* sigma_star, const double* v, double dt,
+                           double* sigma_out) {
+  if (!hd || !sigma_star || !v || !sigma_out) return QS_ERR_ARG;
+  launch_stress_update(sigma_star, v, sigma_out, hd->L[0].d, hd->p.h, dt, hd->p.lambda, hd->p.mu,
+                       hd->stream);
+  return launch_check();
+}
+
+qs_status qs_step_scratch_bytes(qs_handle* hd, size_t* bytes) {
+  if (!hd || !bytes) return QS_ERR_ARG;
+  *bytes = step_scratch(hd);
+  return QS_OK;
+}
+
+qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double* v,
+                             double* sigma, double* chi, void* scratch, double rtol,
+                             int max_cycles, qs_solve_info* info) {
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || max_cycles < 0)
+    return QS_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
+  const Dims d = hd->L[0].d;
+  Carver cv{static_cast<char*>(scratch)};
+  double* sstar = cv.take<double>(6 * cells(d));
+  double* chi1 = cv.take<double>(cells(d));
+  double* b = cv.take<double>(d.elems());
+  const StzArgs a = stz_args(hd, sp);
+  launch_stz_step(v, sigma, chi, sstar, chi1, d, a, hd->stream);
+  launch_set_walls(v, d, U_wall, hd->stream);
+  launch_rhs(sstar, b, d, hd->p.h, sp->dt, hd->stream);
+  qs_status st = launch_check();
+  if (st != QS_OK) return st;
+  st = solve_impl(hd, b, v, rtol, max_cycles, info);
+  if (st != QS_OK && st != QS_ERR_NOT_CONVERGED) return st;
+  launch_stress_update(sstar, v, sigma, d, hd->p.h, sp->dt, hd->p.lambda, hd->p.mu, hd->stream);
+  if (hipMemcpyAsync(chi, chi1, cells(d) * sizeof(double), hipMemcpyDeviceToDevice, hd->stream) !=
+      hipSuccess)
+    return QS_ERR_HIP;
+  const qs_status lc = launch_check();
+  return lc != QS_OK ? lc : st;
+}
+
+qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* v,
+                          const double* sigma, const double* chi, const double* g_sstar,
+                          const double* g_chi1, double* g_sigma, double* g_chi, double* g_v,
+                          void* scratch) {
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !g_sstar || !g_chi1 || !g_sigma || !g_chi ||
+      !g_v || !scratch)
+    return QS_ERR_ARG;
+  const Dims d = hd->L[0].d;
+  double* gL = static_cast<double*>(scratch);
+  const StzArgs a = stz_args(hd, sp);
+  launch_stz_step_vjp(v, sigma, chi, g_sstar, g_chi1, g_sigma, g_chi, gL, d, a, hd->stream);
+  launch_grad_transpose_add(gL, g_v, d, hd->p.h, 1.0, hd->stream);
+  return launch_check();
+}
+
+qs_status qs_rhs_vjp(qs_handle* hd, const double* g_b, double dt, double* g_sstar) {
+  if (!hd || !g_b || !g_sstar || !(dt != 0.0)) return QS_ERR_ARG;
+  launch_rhs_vjp(g_b, g_sstar, hd->L[0].d, hd->p.h, dt, hd->stream);
+  return launch_check();
+}
+
+qs_status qs_stress_update_vjp(qs_handle* hd, const double* g_sigma, double dt, double* g_v) {
+  if (!hd || !g_sigma || !g_v) return QS_ERR_ARG;
+  launch_stress_update_vjp(g_sigma, g_v, hd->L[0].d, hd->p.h, dt, hd->p.lambda, hd->p.mu,
+                           hd->stream);
+  return launch_check();
+}
+
+// ---- test-facing level pieces (FP64 handles) ------------------------------
+
+qs_status qs_level_colour_pass(qs_handle* hd, int level, double* x, const double* b, int colour) {
+  if (!hd || hd->p.precision != QS_FP64 || level < 0 || level >= hd->nlev - 1 || !x || !b ||
+      colour < 0 || colour > 7)
+    return QS_ERR_ARG;
+  colour_pass<double>(hd, level, x, b, colour);
+  return launch_check();
+}
+
+qs_status qs_level_residual(qs_handle* hd, int level, const double* x, const double* b, double* r) {
+  if (!hd || hd->p.precision != QS_FP64 || level < 0 || level >= hd->nlev || !x || !b || !r)
+    return QS_ERR_ARG;
+  residual<double>(hd, level, x, b, r, false);
+  return launch_check();
+}
+
+qs_status qs_level_restrict(qs_handle* hd, int level, const double* r, double* b_coarse) {
+  if (!hd || level < 0 || level >= hd->nlev - 1 || !r || !b_coarse) return QS_ERR_ARG;
+  launch_restrict<double>(r, b_coarse, hd->L[level].d, hd->stream);
+  return launch_check();
+}
+
+qs_status qs_level_prolong_add(qs_handle* hd, int level, double* x, const double* e_coarse) {
+  if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !e_coarse) return QS_ERR_ARG;
+  launch_prolong_add<double>(x, e_coarse, hd->L[level].d, hd->stream);
+  return launch_check();
+}
+
+qs_status qs_coarse_solve(qs_handle* hd, double* x, const double* b) {
+  if (!hd || hd->p.precision != QS_FP64 || !x || !b) return QS_ERR_ARG;
+  const int l = hd->nlev - 1;
+  LevelBufs& lb = hd->L[l];
+  residual<double>(hd, l, x, b, lb.r64, true);
+  launch_coarse_solve<double>(hd->Ainv, hd->ncoarse, lb.r64, x, lb.d, hd->ctin, hd->ctout,
+                              hd->stream);
+  return launch_check();
+}
+
+qs_status qs_smooth(qs_handle* hd, int level, void* x, const void* b, int sweeps) {
+  if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !b || sweeps < 0) return QS_ERR_ARG;
+  const int* ord = hd->p.colour_order;
+  for (int s = 0; s < sweeps; ++s)
+    for (int q = 0; q < 8; ++q) {
+      if (hd->p.precision == QS_FP32_IR)
+        colour_pass<float>(hd, level, static_cast<float*>(x), static_cast<const float*>(b), ord[q]);
+      else
+        colour_pass<double>(hd, level, static_cast<double*>(x), static_cast<const double*>(b),
+                            ord[q]);
+    }
+  return launch_check();
+}
+
+qs_status qs_level_stencil(qs_handle* hd, int level, double* out_host) {
+  if (!hd || level < 0 || level >= hd->nlev || !out_host) return QS_ERR_ARG;
+  const LevelBufs& lb = hd->L[level];
+  const size_t n = static_cast<size_t>(lb.d.nz + 1) * kStencil;
+  if (hipMemcpyAsync(out_host, lb.S64, n * sizeof(double), hipMemcpyDeviceToHost, hd->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(hd->stream) != hipSuccess)
+    return QS_ERR_HIP;
+  return QS_OK;
+}
+
+}  // extern "C"

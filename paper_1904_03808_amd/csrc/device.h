@@ -1,0 +1,92 @@
+// Internal launcher declarations shared by the HIP translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace qs {
+
+// Level geometry: node arrays are [3][nz+1][ny][nx], x fastest.
+struct Dims {
+  int nx, ny, nz;
+  int plane() const { return nx * ny; }
+  int comp() const { return (nz + 1) * nx * ny; }  // elements per component
+  size_t elems() const { return 3ull * comp(); }
+};
+
+// Fine-operator coefficients in the form the fine smoother uses:
+//   x_c = (h2 b_c + sum_a kap_ca (x_c(+e_a) + x_c(-e_a)) + m4 * mixed) * inv_diag
+template <typename T>
+struct FineCoef {
+  T h2;        // h^2
+  T p, q;      // lambda + 2 mu (along the component), mu (across it)
+  T m4;        // (lambda + mu) / 4
+  T inv_diag;  // 1 / (2 (lambda + 4 mu))
+  T ih2;       // 1 / h^2 (residual form)
+};
+
+constexpr int kReduceBlock = 256;
+
+// --- multigrid kernels (kernels_mg.hip) -----------------------------------
+template <typename T>
+void launch_colour_fine(T* x, const T* b, Dims d, int colour, const FineCoef<T>& c, hipStream_t s);
+template <typename T>
+void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
+                       hipStream_t s);
+
+// r = b - A x on interior nodes (walls of r = 0).  If `zero_interior`, x's
+// interior is treated as 0 (r = b - A_IB x_B).  If `partial` is non-null,
+// per-block sums of r^2 (in double) go to partial[blockIdx].  `r` may be
+// null (norm only).  Returns the number of blocks used (for the reduction).
+// The output may be scaled: r_out = (b - A x) * out_scale.
+template <typename Tin, typename Tout>
+int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
+                         double out_scale, bool zero_interior, double* partial, hipStream_t s);
+template <typename T>
+int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool zero_interior,
+                        double* partial, hipStream_t s);
+int residual_blocks(Dims d);
+
+template <typename T>
+void launch_restrict(const T* r, T* bc, Dims fine, hipStream_t s);
+template <typename T>
+void launch_prolong_add(T* x, const T* ec, Dims fine, hipStream_t s);
+
+// Deterministic sum of partial[0..n) into out[0].
+void launch_reduce_sum(const double* partial, int n, double* out, hipStream_t s);
+
+template <typename T>
+void launch_fill(T* x, size_t n, T value, hipStream_t s);
+// x interior (double) += scale * e (float), fine level.
+void launch_ir_update(double* x, const float* e, Dims d, double scale, hipStream_t s);
+// Zero the interior planes of a node vector.
+template <typename T>
+void launch_zero_interior(T* x, Dims d, hipStream_t s);
+
+// Coarsest level: x_interior = Ainv * gather(b), computed in double.
+template <typename T>
+void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, double* tmp_in,
+                         double* tmp_out, hipStream_t s);
+
+// --- STZ / projection kernels (kernels_stz.hip) -----------------------------
+struct StzArgs {
+  double s_y, tau0, beta, delta_over_T, c0, chi_inf, dt;
+  double lam, mu, h;
+};
+void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
+                     double* chi1, Dims d, const StzArgs& a, hipStream_t s);
+void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s);
+void launch_stress_update(const double* sstar, const double* v, double* out, Dims d, double h,
+                          double dt, double lam, double mu, hipStream_t s);
+void launch_set_walls(double* v, Dims d, double U, hipStream_t s);
+void launch_stz_step_vjp(const double* v, const double* sigma, const double* chi,
+                         const double* g_sstar, const double* g_chi1, double* g_sigma,
+                         double* g_chi, double* g_L, Dims d, const StzArgs& a, hipStream_t s);
+void launch_grad_transpose_add(const double* g_L, double* g_v, Dims d, double h, double scale,
+                               hipStream_t s);
+void launch_rhs_vjp(const double* g_b, double* g_sstar, Dims d, double h, double dt,
+                    hipStream_t s);
+void launch_stress_update_vjp(const double* g_sigma, double* g_v, Dims d, double h, double dt,
+                              double lam, double mu, hipStream_t s);
+
+}  // namespace qs

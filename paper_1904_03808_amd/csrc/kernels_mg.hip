@@ -1,0 +1,527 @@
+// Multigrid kernels for gfx950 (paper Sec. 3.6).
+//
+// Node vectors are structure-of-arrays [3][nz+1][ny][nx] with x fastest, so
+// consecutive lanes of a 64-wide wavefront touch consecutive x addresses.
+// x and y wrap periodically; planes k = 0 and k = nz are walls and are never
+// written by any kernel here.
+//
+// Smoothing is multicolour block Gauss-Seidel: colour c = (i&1) + 2(j&1) +
+// 4(k&1).  Nodes of one colour are never coupled by the 3x3x3 stencil, so a
+// colour pass updates them in place in any order without races.
+#include <algorithm>
+
+#include "device.h"
+
+namespace qs {
+
+namespace {
+
+struct ColourRange {
+  int a, bb, kfirst, hx, hy, nk;
+  __host__ __device__ int total() const { return hx * hy * nk; }
+};
+
+ColourRange colour_range(Dims d, int colour) {
+  ColourRange r;
+  r.a = colour & 1;
+  r.bb = (colour >> 1) & 1;
+  const int e = (colour >> 2) & 1;
+  r.kfirst = e ? 1 : 2;
+  r.hx = (d.nx - r.a + 1) / 2;
+  r.hy = (d.ny - r.bb + 1) / 2;
+  r.nk = (d.nz - 1 - r.kfirst) >= 0 ? (d.nz - 1 - r.kfirst) / 2 + 1 : 0;
+  return r;
+}
+
+__device__ __forceinline__ int wrap_m(int i, int n) { return i == 0 ? n - 1 : i - 1; }
+__device__ __forceinline__ int wrap_p(int i, int n) { return i == n - 1 ? 0 : i + 1; }
+
+// Sum of the off-diagonal part of the fine operator (times h^2, sign moved
+// to the right-hand side) for component c at node (i, j, k):
+//   sum_a kap_ca (x_c(+e_a) + x_c(-e_a)) + (lam+mu)/4 sum_{d!=c} sum_{s,t} s t x_d(p + s e_c + t e_d)
+template <typename T>
+struct FineNbr {
+  const T* __restrict__ x;
+  int C, P, nx;
+  int k, j, i, im, ip, jm, jp;
+  __device__ T at(int c, int kk, int jj, int ii) const { return x[c * C + kk * P + jj * nx + ii]; }
+  // mixed difference f(+,+) - f(+,-) - f(-,+) + f(-,-) in the (x, y) plane
+  __device__ T mxy(int c) const {
+    return at(c, k, jp, ip) - at(c, k, jm, ip) - at(c, k, jp, im) + at(c, k, jm, im);
+  }
+  __device__ T mxz(int c) const {
+    return at(c, k + 1, j, ip) - at(c, k - 1, j, ip) - at(c, k + 1, j, im) + at(c, k - 1, j, im);
+  }
+  __device__ T myz(int c) const {
+    return at(c, k + 1, jp, i) - at(c, k - 1, jp, i) - at(c, k + 1, jm, i) + at(c, k - 1, jm, i);
+  }
+  __device__ T fx(int c) const { return at(c, k, j, ip) + at(c, k, j, im); }
+  __device__ T fy(int c) const { return at(c, k, jp, i) + at(c, k, jm, i); }
+  __device__ T fz(int c) const { return at(c, k + 1, j, i) + at(c, k - 1, j, i); }
+  __device__ T offdiag(int c, T p, T q, T m4) const {
+    if (c == 0) return p * fx(0) + q * (fy(0) + fz(0)) + m4 * (mxy(1) + mxz(2));
+    if (c == 1) return p * fy(1) + q * (fx(1) + fz(1)) + m4 * (mxy(0) + myz(2));
+    return p * fz(2) + q * (fx(2) + fy(2)) + m4 * (mxz(0) + myz(1));
+  }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_colour_fine(T* __restrict__ x, const T* __restrict__ b,
+                                                     int nx, int ny, int nz, ColourRange cr,
+                                                     FineCoef<T> cf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cr.total()) return;
+  const int ii = t % cr.hx;
+  const int rest = t / cr.hx;
+  const int jj = rest % cr.hy;
+  const int kk = rest / cr.hy;
+  FineNbr<T> n;
+  n.x = x;
+  n.P = nx * ny;
+  n.C = (nz + 1) * n.P;
+  n.nx = nx;
+  n.i = 2 * ii + cr.a;
+  n.j = 2 * jj + cr.bb;
+  n.k = cr.kfirst + 2 * kk;
+  n.im = wrap_m(n.i, nx);
+  n.ip = wrap_p(n.i, nx);
+  n.jm = wrap_m(n.j, ny);
+  n.jp = wrap_p(n.j, ny);
+  const int o = n.k * n.P + n.j * nx + n.i;
+  T v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = (cf.h2 * b[c * n.C + o] + n.offdiag(c, cf.p, cf.q, cf.m4)) * cf.inv_diag;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c * n.C + o] = v[c];
+}
+
+// Generic per-plane 27-point block stencil S[k][o][c][d].
+template <typename T>
+__global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* __restrict__ b,
+                                                    int nx, int ny, int nz, ColourRange cr,
+                                                    const T* __restrict__ S,
+                                                    const T* __restrict__ Dinv) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cr.total()) return;
+  const int ii = t % cr.hx;
+  const int rest = t / cr.hx;
+  const int jj = rest % cr.hy;
+  const int kk = rest / cr.hy;
+  const int i = 2 * ii + cr.a, j = 2 * jj + cr.bb, k = cr.kfirst + 2 * kk;
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
+  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
+  const T* Sk = S + static_cast<size_t>(k) * 243;
+  T acc[3];
+  const int o = k * P + j * nx + i;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
+#pragma unroll
+  for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+      for (int ox = 0; ox < 3; ++ox) {
+        const int q = oz * 9 + oy * 3 + ox;
+        if (q == 13) continue;
+        const int off = (k + oz - 1) * P + ys[oy] * nx + xs[ox];
+        const T n0 = x[off], n1 = x[C + off], n2 = x[2 * C + off];
+        const T* B = Sk + q * 9;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] -= B[c * 3] * n0 + B[c * 3 + 1] * n1 + B[c * 3 + 2] * n2;
+      }
+  const T* Di = Dinv + static_cast<size_t>(k) * 9;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    x[c * C + o] = Di[c * 3] * acc[0] + Di[c * 3 + 1] * acc[1] + Di[c * 3 + 2] * acc[2];
+}
+
+// Block-level sum of one double per thread; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kReduceBlock / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kReduceBlock / 64; ++w) s += red[w];
+  }
+  return s;
+}
+
+template <typename Tin, typename Tout, bool ZERO_INT>
+__global__ __launch_bounds__(kReduceBlock) void k_residual_fine(
+    const Tin* __restrict__ x, const Tin* __restrict__ b, Tout* __restrict__ r, int nx, int ny,
+    int nz, FineCoef<Tin> cf, Tin out_scale, double* __restrict__ partial) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = nx * ny * (nz - 1);
+  double sq = 0.0;
+  if (t < total) {
+    FineNbr<Tin> n;
+    n.x = x;
+    n.P = nx * ny;
+    n.C = (nz + 1) * n.P;
+    n.nx = nx;
+    n.i = t % nx;
+    n.j = (t / nx) % ny;
+    n.k = 1 + t / n.P;
+    n.im = wrap_m(n.i, nx);
+    n.ip = wrap_p(n.i, nx);
+    n.jm = wrap_m(n.j, ny);
+    n.jp = wrap_p(n.j, ny);
+    const int o = n.k * n.P + n.j * nx + n.i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      Tin off;
+      if (ZERO_INT) {
+        // only the wall planes contribute: nodes of plane k-1 or k+1 that are walls
+        off = Tin(0);
+        // only couplings into the wall planes remain: the face neighbour
+        // across the wall and the mixed differences reaching it
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const bool touches = side == 0 ? (n.k == 1) : (n.k == nz - 1);
+          if (!touches) continue;
+          const int w = side == 0 ? 0 : nz;
+          const Tin sg = side == 0 ? Tin(-1) : Tin(1);
+          const Tin fz = n.at(c, w, n.j, n.i);
+          Tin mix;
+          if (c == 0)
+            mix = sg * (n.at(2, w, n.j, n.ip) - n.at(2, w, n.j, n.im));
+          else if (c == 1)
+            mix = sg * (n.at(2, w, n.jp, n.i) - n.at(2, w, n.jm, n.i));
+          else
+            mix = sg * (n.at(0, w, n.j, n.ip) - n.at(0, w, n.j, n.im) + n.at(1, w, n.jp, n.i) -
+                        n.at(1, w, n.jm, n.i));
+          off += (c == 2 ? cf.p : cf.q) * fz + cf.m4 * mix;
+        }
+        const Tin bv = b ? b[c * n.C + o] : Tin(0);
+        const Tin res = bv + off * cf.ih2;
+        sq += static_cast<double>(res) * static_cast<double>(res);
+        if (r) r[c * n.C + o] = static_cast<Tout>(res * out_scale);
+      } else {
+        off = n.offdiag(c, cf.p, cf.q, cf.m4);
+        const Tin diag = Tin(2) * (cf.p + Tin(2) * cf.q);
+        const Tin bv = b ? b[c * n.C + o] : Tin(0);
+        const Tin res = bv - (diag * n.at(c, n.k, n.j, n.i) - off) * cf.ih2;
+        sq += static_cast<double>(res) * static_cast<double>(res);
+        if (r) r[c * n.C + o] = static_cast<Tout>(res * out_scale);
+      }
+    }
+  }
+  if (partial) {
+    const double s = block_sum(sq);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+template <typename T, bool ZERO_INT>
+__global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restrict__ x,
+                                                               const T* __restrict__ b,
+                                                               T* __restrict__ r, int nx, int ny,
+                                                               int nz, const T* __restrict__ S,
+                                                               double* __restrict__ partial) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = nx * ny * (nz - 1);
+  double sq = 0.0;
+  if (t < total) {
+    const int P = nx * ny, C = (nz + 1) * P;
+    const int i = t % nx, j = (t / nx) % ny, k = 1 + t / P;
+    const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
+    const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
+    const T* Sk = S + static_cast<size_t>(k) * 243;
+    const int o = k * P + j * nx + i;
+    T acc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz) {
+      const int kk = k + oz - 1;
+      if (ZERO_INT && kk != 0 && kk != nz) continue;
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+          const int q = oz * 9 + oy * 3 + ox;
+          const int off = kk * P + ys[oy] * nx + xs[ox];
+          const T n0 = x[off], n1 = x[C + off], n2 = x[2 * C + off];
+          const T* B = Sk + q * 9;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            acc[c] -= B[c * 3] * n0 + B[c * 3 + 1] * n1 + B[c * 3 + 2] * n2;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      sq += static_cast<double>(acc[c]) * static_cast<double>(acc[c]);
+      if (r) r[c * C + o] = acc[c];
+    }
+  }
+  if (partial) {
+    const double s = block_sum(sq);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// b_c(I) = sum over the 27 fine nodes around 2I of w * r(f), w = prod (1 or 1/2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __restrict__ bc,
+                                                  int nxf, int nyf, int nzf) {
+  const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = nxc * nyc * (nzc - 1);
+  if (t >= total) return;
+  const int I = t % nxc, J = (t / nxc) % nyc, K = 1 + t / (nxc * nyc);
+  const int Pf = nxf * nyf, Cf = (nzf + 1) * Pf;
+  const int Pc = nxc * nyc, Cc = (nzc + 1) * Pc;
+  const int xs[3] = {wrap_m(2 * I, nxf), 2 * I, 2 * I + 1};
+  const int ys[3] = {wrap_m(2 * J, nyf), 2 * J, 2 * J + 1};
+  const T w[3] = {T(0.5), T(1), T(0.5)};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T acc = T(0);
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+      const int kf = 2 * K + dz - 1;
+      T az = T(0);
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const T* row = r + c * Cf + kf * Pf + ys[dy] * nxf;
+        const T ax = T(0.5) * row[xs[0]] + row[xs[1]] + T(0.5) * row[xs[2]];
+        az += w[dy] * ax;
+      }
+      acc += w[dz] * az;
+    }
+    bc[c * Cc + K * Pc + J * nxc + I] = acc;
+  }
+}
+
+// x(f) += sum_J w(f - 2J) e(J) over the (up to 8) coarse nodes around f.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T* __restrict__ ec,
+                                                     int nxf, int nyf, int nzf) {
+  const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = nxf * nyf * (nzf - 1);
+  if (t >= total) return;
+  const int i = t % nxf, j = (t / nxf) % nyf, k = 1 + t / (nxf * nyf);
+  const int Pf = nxf * nyf, Cf = (nzf + 1) * Pf;
+  const int Pc = nxc * nyc, Cc = (nzc + 1) * Pc;
+  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
+  const int i1 = (i & 1) ? (i0 + 1 == nxc ? 0 : i0 + 1) : i0;
+  const int j1 = (j & 1) ? (j0 + 1 == nyc ? 0 : j0 + 1) : j0;
+  const int k1 = (k & 1) ? k0 + 1 : k0;
+  const T wx = (i & 1) ? T(0.5) : T(1), wy = (j & 1) ? T(0.5) : T(1), wz = (k & 1) ? T(0.5) : T(1);
+  // with an even index both "neighbours" coincide and carry weight 1 once
+  const bool ox = i & 1, oy = j & 1, oz = k & 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T* E = ec + c * Cc;
+    auto row = [&](int kk, int jj) {
+      const T* p = E + kk * Pc + jj * nxc;
+      return ox ? wx * (p[i0] + p[i1]) : p[i0];
+    };
+    auto plane = [&](int kk) { return oy ? wy * (row(kk, j0) + row(kk, j1)) : row(kk, j0); };
+    const T add = oz ? wz * (plane(k0) + plane(k1)) : plane(k0);
+    x[c * Cf + k * Pf + j * nxf + i] += add;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_sum(const double* __restrict__ partial, int n,
+                                                     double* __restrict__ out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) s += partial[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    out[0] = t;
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, size_t n, T v) {
+  size_t t = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x;
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (; t < n; t += stride) x[t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_ir_update(double* __restrict__ x, const float* __restrict__ e,
+                                                   int nx, int ny, int nz, double scale) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = nx * ny, per = P * (nz - 1);
+  if (t >= 3 * per) return;
+  const int c = t / per, rem = t - c * per;
+  const size_t o = static_cast<size_t>(c) * (nz + 1) * P + P + rem;
+  x[o] += scale * static_cast<double>(e[o]);
+}
+
+template <typename T>
+__global__ void k_gather(const T* __restrict__ b, double* __restrict__ out, int nx, int ny, int nz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = nx * ny, per = P * (nz - 1);
+  if (t >= 3 * per) return;
+  const int c = t / per, rem = t - c * per;
+  out[t] = static_cast<double>(b[static_cast<size_t>(c) * (nz + 1) * P + P + rem]);
+}
+
+template <typename T>
+__global__ void k_scatter(const double* __restrict__ in, T* __restrict__ x, int nx, int ny, int nz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = nx * ny, per = P * (nz - 1);
+  if (t >= 3 * per) return;
+  const int c = t / per, rem = t - c * per;
+  x[static_cast<size_t>(c) * (nz + 1) * P + P + rem] = static_cast<T>(in[t]);
+}
+
+// One 64-lane wavefront per row of the dense coarsest inverse.
+__global__ __launch_bounds__(256) void k_dense_matvec(const double* __restrict__ A,
+                                                      const double* __restrict__ v,
+                                                      double* __restrict__ out, int n) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* a = A + static_cast<size_t>(row) * n;
+  double s = 0.0;
+  for (int q = lane; q < n; q += 64) s += a[q] * v[q];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) out[row] = s;
+}
+
+inline int blocks_for(long long n, int bs) { return static_cast<int>((n + bs - 1) / bs); }
+
+}  // namespace
+
+template <typename T>
+void launch_colour_fine(T* x, const T* b, Dims d, int colour, const FineCoef<T>& c, hipStream_t s) {
+  const ColourRange cr = colour_range(d, colour);
+  if (cr.total() <= 0) return;
+  hipLaunchKernelGGL(k_colour_fine<T>, dim3(blocks_for(cr.total(), 256)), dim3(256), 0, s, x, b,
+                     d.nx, d.ny, d.nz, cr, c);
+}
+
+template <typename T>
+void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
+                       hipStream_t s) {
+  const ColourRange cr = colour_range(d, colour);
+  if (cr.total() <= 0) return;
+  hipLaunchKernelGGL(k_colour_gen<T>, dim3(blocks_for(cr.total(), 256)), dim3(256), 0, s, x, b,
+                     d.nx, d.ny, d.nz, cr, S, Dinv);
+}
+
+int residual_blocks(Dims d) { return blocks_for(static_cast<long long>(d.nx) * d.ny * (d.nz - 1), kReduceBlock); }
+
+template <typename Tin, typename Tout>
+int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
+                         double out_scale, bool zero_interior, double* partial, hipStream_t s) {
+  FineCoef<Tin> cf;
+  cf.h2 = static_cast<Tin>(c.h2);
+  cf.p = static_cast<Tin>(c.p);
+  cf.q = static_cast<Tin>(c.q);
+  cf.m4 = static_cast<Tin>(c.m4);
+  cf.inv_diag = static_cast<Tin>(c.inv_diag);
+  cf.ih2 = static_cast<Tin>(c.ih2);
+  const int nb = residual_blocks(d);
+  if (zero_interior)
+    hipLaunchKernelGGL((k_residual_fine<Tin, Tout, true>), dim3(nb), dim3(kReduceBlock), 0, s, x, b,
+                       r, d.nx, d.ny, d.nz, cf, static_cast<Tin>(out_scale), partial);
+  else
+    hipLaunchKernelGGL((k_residual_fine<Tin, Tout, false>), dim3(nb), dim3(kReduceBlock), 0, s, x,
+                       b, r, d.nx, d.ny, d.nz, cf, static_cast<Tin>(out_scale), partial);
+  return nb;
+}
+
+template <typename T>
+int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool zero_interior,
+                        double* partial, hipStream_t s) {
+  const int nb = residual_blocks(d);
+  if (zero_interior)
+    hipLaunchKernelGGL((k_residual_gen<T, true>), dim3(nb), dim3(kReduceBlock), 0, s, x, b, r, d.nx,
+                       d.ny, d.nz, S, partial);
+  else
+    hipLaunchKernelGGL((k_residual_gen<T, false>), dim3(nb), dim3(kReduceBlock), 0, s, x, b, r,
+                       d.nx, d.ny, d.nz, S, partial);
+  return nb;
+}
+
+template <typename T>
+void launch_restrict(const T* r, T* bc, Dims f, hipStream_t s) {
+  const long long total = static_cast<long long>(f.nx / 2) * (f.ny / 2) * (f.nz / 2 - 1);
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, r, bc, f.nx,
+                     f.ny, f.nz);
+}
+
+template <typename T>
+void launch_prolong_add(T* x, const T* ec, Dims f, hipStream_t s) {
+  const long long total = static_cast<long long>(f.nx) * f.ny * (f.nz - 1);
+  hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, ec, f.nx,
+                     f.ny, f.nz);
+}
+
+void launch_reduce_sum(const double* partial, int n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(1024), 0, s, partial, n, out);
+}
+
+template <typename T>
+void launch_fill(T* x, size_t n, T value, hipStream_t s) {
+  if (n == 0) return;
+  const int nb = static_cast<int>(std::min<size_t>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_fill<T>, dim3(nb), dim3(256), 0, s, x, n, value);
+}
+
+void launch_ir_update(double* x, const float* e, Dims d, double scale, hipStream_t s) {
+  const long long total = 3LL * d.nx * d.ny * (d.nz - 1);
+  hipLaunchKernelGGL(k_ir_update, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, e, d.nx, d.ny,
+                     d.nz, scale);
+}
+
+template <typename T>
+void launch_zero_interior(T* x, Dims d, hipStream_t s) {
+  for (int c = 0; c < 3; ++c)
+    launch_fill<T>(x + static_cast<size_t>(c) * d.comp() + d.plane(),
+                   static_cast<size_t>(d.plane()) * (d.nz - 1), T(0), s);
+}
+
+template <typename T>
+void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, double* tin,
+                         double* tout, hipStream_t s) {
+  const int nb = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_gather<T>, dim3(nb), dim3(256), 0, s, b, tin, d.nx, d.ny, d.nz);
+  hipLaunchKernelGGL(k_dense_matvec, dim3(blocks_for(n, 4)), dim3(256), 0, s, Ainv, tin, tout, n);
+  hipLaunchKernelGGL(k_scatter<T>, dim3(nb), dim3(256), 0, s, tout, x, d.nx, d.ny, d.nz);
+}
+
+#define QS_INST(T)                                                                               \
+  template void launch_colour_fine<T>(T*, const T*, Dims, int, const FineCoef<T>&, hipStream_t); \
+  template void launch_colour_gen<T>(T*, const T*, Dims, int, const T*, const T*, hipStream_t);  \
+  template int launch_residual_gen<T>(const T*, const T*, T*, Dims, const T*, bool, double*,     \
+                                      hipStream_t);                                              \
+  template void launch_restrict<T>(const T*, T*, Dims, hipStream_t);                             \
+  template void launch_prolong_add<T>(T*, const T*, Dims, hipStream_t);                          \
+  template void launch_fill<T>(T*, size_t, T, hipStream_t);                                      \
+  template void launch_zero_interior<T>(T*, Dims, hipStream_t);                                  \
+  template void launch_coarse_solve<T>(const double*, int, const T*, T*, Dims, double*, double*, \
+                                       hipStream_t);
+QS_INST(double)
+QS_INST(float)
+#undef QS_INST
+template int launch_residual_fine<double, double>(const double*, const double*, double*, Dims,
+                                                  const FineCoef<double>&, double, bool, double*,
+                                                  hipStream_t);
+template int launch_residual_fine<double, float>(const double*, const double*, float*, Dims,
+                                                 const FineCoef<double>&, double, bool, double*,
+                                                 hipStream_t);
+template int launch_residual_fine<float, float>(const float*, const float*, float*, Dims,
+                                                const FineCoef<double>&, double, bool, double*,
+                                                hipStream_t);
+
+}  // namespace qs

@@ -1,0 +1,517 @@
+// Pointwise STZ update, projection right-hand side and stress correction
+// (paper Secs. 3.1, 3.3, 3.4), and their reverse-mode derivatives.
+//
+// Cell tensors are [6][nz][ny][nx] in Voigt order (xx, yy, zz, yz, xz, xy);
+// cell (i,j,k) has corners i..i+1, j..j+1 (wrapped), k..k+1.  Node vectors
+// are [3][nz+1][ny][nx].  One thread per cell or per interior node; these
+// kernels stream their inputs once and are HBM-bound.
+#include "device.h"
+
+namespace qs {
+
+namespace {
+
+constexpr int VA[6] = {0, 1, 2, 1, 0, 0};
+constexpr int VB[6] = {0, 1, 2, 2, 2, 1};
+
+struct CellIdx {
+  int i, j, k, ip, jp;
+};
+
+__device__ __forceinline__ bool cell_of(int t, int nx, int ny, int nz, CellIdx* c) {
+  if (t >= nx * ny * nz) return false;
+  c->i = t % nx;
+  c->j = (t / nx) % ny;
+  c->k = t / (nx * ny);
+  c->ip = c->i + 1 == nx ? 0 : c->i + 1;
+  c->jp = c->j + 1 == ny ? 0 : c->j + 1;
+  return true;
+}
+
+// Velocity gradient L[a][b] = d v_a / d x_b at a cell centre: the average of
+// the four edge differences parallel to x_b (Eq. stag_stenc).
+__device__ __forceinline__ void cell_gradient(const double* __restrict__ v, int nx, int ny, int nz,
+                                              const CellIdx& c, double ih4, double L[3][3]) {
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int xs[2] = {c.i, c.ip}, ys[2] = {c.j, c.jp};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double f[2][2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) f[dz][dy][dx] = v[a * C + (c.k + dz) * P + ys[dy] * nx + xs[dx]];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        gx += f[p][q][1] - f[p][q][0];
+        gy += f[p][1][q] - f[p][0][q];
+        gz += f[1][p][q] - f[0][p][q];
+      }
+    L[a][0] = gx * ih4;
+    L[a][1] = gy * ih4;
+    L[a][2] = gz * ih4;
+  }
+}
+
+__device__ __forceinline__ void load_voigt(const double* __restrict__ s, int N, int o, double S[3][3]) {
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const double val = s[n * N + o];
+    S[VA[n]][VB[n]] = val;
+    S[VB[n]][VA[n]] = val;
+  }
+}
+
+// Scalar plastic rate of Eq. stz_dpl and its partial derivatives in sbar
+// and chi; zero (with zero derivatives) at or below yield.
+struct Plastic {
+  double D, dD_ds, dD_dchi;
+};
+
+__device__ __forceinline__ Plastic plastic_rate(double sbar, double chi, const StzArgs& a) {
+  Plastic p{0.0, 0.0, 0.0};
+  if (sbar > a.s_y) {
+    const double A = exp(-1.0 / chi) * exp(-a.delta_over_T) / a.tau0;
+    const double bs = a.beta * sbar;
+    const double ch = cosh(bs), sh = sinh(bs);
+    const double f = 1.0 - a.s_y / sbar;
+    p.D = A * ch * f;
+    p.dD_ds = A * (a.beta * sh * f + ch * a.s_y / (sbar * sbar));
+    p.dD_dchi = p.D / (chi * chi);
+  }
+  return p;
+}
+
+__device__ __forceinline__ void deviator(const double S[3][3], double S0[3][3], double* sbar) {
+  const double pr = (S[0][0] + S[1][1] + S[2][2]) * (1.0 / 3.0);
+  double q = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      S0[a][b] = S[a][b] - (a == b ? pr : 0.0);
+      q += S0[a][b] * S0[a][b];
+    }
+  *sbar = sqrt(0.5 * q);
+}
+
+__global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
+                                                  const double* __restrict__ sigma,
+                                                  const double* __restrict__ chi,
+                                                  double* __restrict__ sstar,
+                                                  double* __restrict__ chi1, int nx, int ny, int nz,
+                                                  StzArgs a) {
+  CellIdx c;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!cell_of(t, nx, ny, nz, &c)) return;
+  const int N = nx * ny * nz;
+  double L[3][3], S[3][3], S0[3][3], sbar;
+  cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
+  load_voigt(sigma, N, t, S);
+  deviator(S, S0, &sbar);
+  const double x = chi[t];
+  const Plastic pl = plastic_rate(sbar, x, a);
+  const double rho = pl.D > 0.0 ? pl.D / sbar : 0.0;
+  const double trL = L[0][0] + L[1][1] + L[2][2];
+  // C : (rho S0) = lambda tr(rho S0) I + 2 mu rho S0, and tr(S0) = 0
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const int p = VA[n], q = VB[n];
+    double LS = 0.0, SLt = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      LS += L[p][m] * S[m][q];
+      SLt += S[p][m] * L[q][m];
+    }
+    const double rate = LS + SLt - trL * S[p][q] - 2.0 * a.mu * rho * S0[p][q];
+    sstar[n * N + t] = S[p][q] + a.dt * rate;
+  }
+  chi1[t] = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
+}
+
+// Node divergence of a cell field (corner form of Eq. stag_stenc): for
+// interior node (i,j,k) the cells (i-1..i, j-1..j, k-1..k).  `get(n, cell)`
+// returns component n of the tensor stored per cell.
+struct NodeCells {
+  int cell[2][2][2];  // [ez][ey][ex] -> flat cell index
+};
+
+__device__ __forceinline__ bool node_of(int t, int nx, int ny, int nz, int* i, int* j, int* k,
+                                        NodeCells* nc) {
+  if (t >= nx * ny * (nz - 1)) return false;
+  *i = t % nx;
+  *j = (t / nx) % ny;
+  *k = 1 + t / (nx * ny);
+  const int xs[2] = {*i == 0 ? nx - 1 : *i - 1, *i};
+  const int ys[2] = {*j == 0 ? ny - 1 : *j - 1, *j};
+#pragma unroll
+  for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+      for (int ex = 0; ex < 2; ++ex) nc->cell[ez][ey][ex] = ((*k - 1 + ez) * ny + ys[ey]) * nx + xs[ex];
+  return true;
+}
+
+// d/dx_b at a node of a cell scalar g given its 8 values g[ez][ey][ex].
+__device__ __forceinline__ double node_diff(const double g[2][2][2], int b) {
+  double s = 0.0;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (b == 0) s += g[p][q][1] - g[p][q][0];
+      if (b == 1) s += g[p][1][q] - g[p][0][q];
+      if (b == 2) s += g[1][p][q] - g[0][p][q];
+    }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ sstar, double* __restrict__ b,
+                                             int nx, int ny, int nz, double scale) {
+  int i, j, k;
+  NodeCells nc;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!node_of(t, nx, ny, nz, &i, &j, &k, &nc)) return;
+  const int N = nx * ny * nz, P = nx * ny, C = (nz + 1) * P;
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    double g[2][2][2];
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) g[ez][ey][ex] = sstar[n * N + nc.cell[ez][ey][ex]];
+    const int p = VA[n], q = VB[n];
+    acc[p] += node_diff(g, q);
+    if (p != q) acc[q] += node_diff(g, p);
+  }
+  const int o = k * P + j * nx + i;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) b[a * C + o] = acc[a] * scale;
+}
+
+__global__ void k_zero_walls(double* __restrict__ b, int nx, int ny, int nz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = nx * ny;
+  if (t >= 6 * P) return;
+  const int c = t / (2 * P), rem = t % (2 * P);
+  const int plane = rem < P ? 0 : nz;
+  b[(static_cast<size_t>(c) * (nz + 1) + plane) * P + rem % P] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_stress_update(const double* __restrict__ sstar,
+                                                       const double* __restrict__ v,
+                                                       double* __restrict__ out, int nx, int ny,
+                                                       int nz, double h, double dt, double lam,
+                                                       double mu) {
+  CellIdx c;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!cell_of(t, nx, ny, nz, &c)) return;
+  const int N = nx * ny * nz;
+  double L[3][3];
+  cell_gradient(v, nx, ny, nz, c, 0.25 / h, L);
+  const double tr = L[0][0] + L[1][1] + L[2][2];
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const int p = VA[n], q = VB[n];
+    const double D = 0.5 * (L[p][q] + L[q][p]);
+    out[n * N + t] = sstar[n * N + t] + dt * ((p == q ? lam * tr : 0.0) + 2.0 * mu * D);
+  }
+}
+
+__global__ void k_set_walls(double* __restrict__ v, int nx, int ny, int nz, double U) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = nx * ny;
+  if (t >= 2 * P) return;
+  const int plane = t < P ? 0 : nz;
+  const size_t o = static_cast<size_t>(plane) * P + (t % P);
+  const size_t C = static_cast<size_t>(nz + 1) * P;
+  v[o] = plane == 0 ? -U : U;
+  v[C + o] = 0.0;
+  v[2 * C + o] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse mode.  All cotangents are derivatives with respect to the stored
+// numbers (Euclidean inner product on the arrays).
+// ---------------------------------------------------------------------------
+
+// Per cell: cotangents of sigma (Voigt), chi and the velocity gradient L
+// (9 values, [a][b] row-major, stored as [9][cells]) from those of sigma*
+// and chi'.
+__global__ __launch_bounds__(256) void k_stz_step_vjp(
+    const double* __restrict__ v, const double* __restrict__ sigma, const double* __restrict__ chi,
+    const double* __restrict__ g_sstar, const double* __restrict__ g_chi1,
+    double* __restrict__ g_sigma, double* __restrict__ g_chi, double* __restrict__ g_L, int nx,
+    int ny, int nz, StzArgs a) {
+  CellIdx c;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!cell_of(t, nx, ny, nz, &c)) return;
+  const int N = nx * ny * nz;
+  double L[3][3], S[3][3], S0[3][3], sbar, W[3][3];
+  cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
+  load_voigt(sigma, N, t, S);
+  deviator(S, S0, &sbar);
+  // f = sum_n g_n sigma*_n = W : S* with W symmetric, W_ab = g_n (a==b) or g_n/2
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const double g = g_sstar[n * N + t];
+    const int p = VA[n], q = VB[n];
+    if (p == q) {
+      W[p][p] = g;
+    } else {
+      W[p][q] = 0.5 * g;
+      W[q][p] = 0.5 * g;
+    }
+  }
+  const double x = chi[t];
+  const double gc = g_chi1[t];
+  const Plastic pl = plastic_rate(sbar, x, a);
+  const bool act = pl.D > 0.0;
+  const double rho = act ? pl.D / sbar : 0.0;
+  const double trL = L[0][0] + L[1][1] + L[2][2];
+  double WS[3][3], WdotS = 0.0;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) s += W[p][m] * S[m][q];
+      WS[p][q] = s;
+      WdotS += W[p][q] * S[p][q];
+    }
+  // dL: dt (2 (W S) - tr(W:S) I)
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      g_L[(p * 3 + q) * N + t] = a.dt * (2.0 * WS[p][q] - (p == q ? WdotS : 0.0));
+  // H = df/dS over all nine entries
+  const double trW = W[0][0] + W[1][1] + W[2][2];
+  double W0[3][3], W0dotS = 0.0;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      W0[p][q] = W[p][q] - (p == q ? trW / 3.0 : 0.0);
+      W0dotS += W0[p][q] * S[p][q];
+    }
+  double H[3][3];
+  // coefficient multiplying S0 / (2 sbar) from the sbar-dependence
+  double dsb = 0.0;
+  double gchi = 0.0;
+  const double kq = 2.0 * a.dt / (a.c0 * a.s_y);
+  if (act) {
+    const double drho = pl.dD_ds / sbar - pl.D / (sbar * sbar);
+    dsb += -2.0 * a.mu * a.dt * W0dotS * drho;
+    dsb += gc * kq * (a.chi_inf - x) * (pl.D + sbar * pl.dD_ds);
+    gchi += -2.0 * a.mu * a.dt * W0dotS * pl.dD_dchi / sbar;
+    gchi += gc * kq * (sbar * pl.dD_dchi * (a.chi_inf - x) - sbar * pl.D);
+  }
+  gchi += gc;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double LtW = 0.0, WL = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        LtW += L[m][p] * W[m][q];
+        WL += W[p][m] * L[m][q];
+      }
+      double hpq = W[p][q] + a.dt * (LtW + WL - trL * W[p][q]);
+      if (act) hpq += -2.0 * a.mu * a.dt * rho * W0[p][q] + dsb * S0[p][q] / (2.0 * sbar);
+      H[p][q] = hpq;
+    }
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const int p = VA[n], q = VB[n];
+    g_sigma[n * N + t] = p == q ? H[p][p] : H[p][q] + H[q][p];
+  }
+  g_chi[t] = gchi;
+}
+
+// g_v_a(node) += scale * (G_h^T T)_a = -scale * sum_b d_b T_ab at interior
+// nodes, T a full 3x3 cell tensor stored [9][cells].
+__global__ __launch_bounds__(256) void k_grad_transpose_add(const double* __restrict__ T,
+                                                            double* __restrict__ g_v, int nx,
+                                                            int ny, int nz, double ih4,
+                                                            double scale) {
+  int i, j, k;
+  NodeCells nc;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!node_of(t, nx, ny, nz, &i, &j, &k, &nc)) return;
+  const int N = nx * ny * nz, P = nx * ny, C = (nz + 1) * P;
+  const int o = k * P + j * nx + i;
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double g[2][2][2];
+#pragma unroll
+      for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+          for (int ex = 0; ex < 2; ++ex) g[ez][ey][ex] = T[(p * 3 + q) * N + nc.cell[ez][ey][ex]];
+      acc += node_diff(g, q);
+    }
+    g_v[p * C + o] -= scale * ih4 * acc;
+  }
+}
+
+// g_sstar_n += -(1/dt) (G or G + G^T)_n with G = G_h g_b (walls of g_b as 0).
+__global__ __launch_bounds__(256) void k_rhs_vjp(const double* __restrict__ g_b,
+                                                 double* __restrict__ g_sstar, int nx, int ny,
+                                                 int nz, double ih4, double scale) {
+  CellIdx c;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!cell_of(t, nx, ny, nz, &c)) return;
+  const int N = nx * ny * nz, P = nx * ny, C = (nz + 1) * P;
+  const int xs[2] = {c.i, c.ip}, ys[2] = {c.j, c.jp};
+  double G[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double f[2][2][2];
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int kk = c.k + dz;
+      const bool wall = (kk == 0 || kk == nz);
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx)
+          f[dz][dy][dx] = wall ? 0.0 : g_b[a * C + kk * P + ys[dy] * nx + xs[dx]];
+    }
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        gx += f[p][q][1] - f[p][q][0];
+        gy += f[p][1][q] - f[p][0][q];
+        gz += f[1][p][q] - f[0][p][q];
+      }
+    G[a][0] = gx * ih4;
+    G[a][1] = gy * ih4;
+    G[a][2] = gz * ih4;
+  }
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const int p = VA[n], q = VB[n];
+    const double val = p == q ? G[p][p] : G[p][q] + G[q][p];
+    g_sstar[n * N + t] -= scale * val;
+  }
+}
+
+// g_v += G_h^T T(g_sigma), T_cd = dt (lam tr(g) delta_cd + mu (2 g_cc or g_{cd})),
+// evaluated per node from the 8 surrounding cells.
+__global__ __launch_bounds__(256) void k_stress_update_vjp(const double* __restrict__ gs,
+                                                           double* __restrict__ g_v, int nx, int ny,
+                                                           int nz, double ih4, double dt,
+                                                           double lam, double mu) {
+  int i, j, k;
+  NodeCells nc;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!node_of(t, nx, ny, nz, &i, &j, &k, &nc)) return;
+  const int N = nx * ny * nz, P = nx * ny, C = (nz + 1) * P;
+  const int o = k * P + j * nx + i;
+  double acc[3] = {0.0, 0.0, 0.0};
+  // T[p][q] per cell is linear in the Voigt cotangent: accumulate d_q T[p][q]
+  // directly from each Voigt component's node derivatives.
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    double g[2][2][2];
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) g[ez][ey][ex] = gs[n * N + nc.cell[ez][ey][ex]];
+    const int p = VA[n], q = VB[n];
+    if (p == q) {
+      // lam * g_pp enters T_aa for every a; 2 mu g_pp enters T_pp
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) acc[aa] += lam * node_diff(g, aa);
+      acc[p] += 2.0 * mu * node_diff(g, p);
+    } else {
+      // mu g_pq enters T_pq and T_qp
+      acc[p] += mu * node_diff(g, q);
+      acc[q] += mu * node_diff(g, p);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) g_v[a * C + o] -= dt * ih4 * acc[a];
+}
+
+inline int blocks_for(long long n, int bs) { return static_cast<int>((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
+                     double* chi1, Dims d, const StzArgs& a, hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
+  hipLaunchKernelGGL(k_stz_step, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi, sstar,
+                     chi1, d.nx, d.ny, d.nz, a);
+}
+
+void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * (d.nz - 1);
+  hipLaunchKernelGGL(k_rhs, dim3(blocks_for(n, 256)), dim3(256), 0, s, sstar, b, d.nx, d.ny, d.nz,
+                     0.25 / (h * dt));
+  hipLaunchKernelGGL(k_zero_walls, dim3(blocks_for(6LL * d.plane(), 256)), dim3(256), 0, s, b,
+                     d.nx, d.ny, d.nz);
+}
+
+void launch_stress_update(const double* sstar, const double* v, double* out, Dims d, double h,
+                          double dt, double lam, double mu, hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
+  hipLaunchKernelGGL(k_stress_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, sstar, v, out,
+                     d.nx, d.ny, d.nz, h, dt, lam, mu);
+}
+
+void launch_set_walls(double* v, Dims d, double U, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_walls, dim3(blocks_for(2LL * d.plane(), 256)), dim3(256), 0, s, v, d.nx,
+                     d.ny, d.nz, U);
+}
+
+void launch_stz_step_vjp(const double* v, const double* sigma, const double* chi,
+                         const double* g_sstar, const double* g_chi1, double* g_sigma,
+                         double* g_chi, double* g_L, Dims d, const StzArgs& a, hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
+  hipLaunchKernelGGL(k_stz_step_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi,
+                     g_sstar, g_chi1, g_sigma, g_chi, g_L, d.nx, d.ny, d.nz, a);
+}
+
+void launch_grad_transpose_add(const double* g_L, double* g_v, Dims d, double h, double scale,
+                               hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * (d.nz - 1);
+  hipLaunchKernelGGL(k_grad_transpose_add, dim3(blocks_for(n, 256)), dim3(256), 0, s, g_L, g_v,
+                     d.nx, d.ny, d.nz, 0.25 / h, scale);
+}
+
+void launch_rhs_vjp(const double* g_b, double* g_sstar, Dims d, double h, double dt,
+                    hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
+  hipLaunchKernelGGL(k_rhs_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, g_b, g_sstar, d.nx,
+                     d.ny, d.nz, 0.25 / h, 1.0 / dt);
+}
+
+void launch_stress_update_vjp(const double* g_sigma, double* g_v, Dims d, double h, double dt,
+                              double lam, double mu, hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * (d.nz - 1);
+  hipLaunchKernelGGL(k_stress_update_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, g_sigma, g_v,
+                     d.nx, d.ny, d.nz, 0.25 / h, dt, lam, mu);
+}
+
+}  // namespace qs

@@ -1,0 +1,229 @@
+"""GPU parity of the multigrid path (libqsmg through its C ABI) against the oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.multigrid import MGOracle, direct_solve
+from oracle.operators import apply_elastic, div_node
+from workloads import lame, stress_field
+
+pytestmark = pytest.mark.gpu
+LAM, MU = lame()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def make(nx, ny, nz, **kw):
+    from paper_1904_03808_amd.qsmg import MGSolver
+    h = 1.0 / nz
+    return MGSolver(nx, ny, nz, h, LAM, MU, **kw), MGOracle(nx, ny, nz, h, LAM, MU,
+                                                           min_coarse_nz=kw.get("min_coarse_nz", 8),
+                                                           order=[(c & 1, (c >> 1) & 1, (c >> 2) & 1)
+                                                                  for c in kw.get("colour_order", range(8))])
+
+
+def rand_node(rng, nx, ny, nz, walls=True):
+    x = rng.standard_normal((3, nz + 1, ny, nx))
+    if not walls:
+        x[:, 0] = 0
+        x[:, -1] = 0
+    return x
+
+
+GRIDS = [(32, 32, 32), (40, 24, 32)]
+
+
+@pytest.mark.parametrize("n", GRIDS)
+def test_stencils_match_oracle(n):
+    """Host Galerkin by stencil composition == oracle Galerkin by sparse RAP."""
+    g, o = make(*n)
+    assert g.levels == len(o.levels)
+    for lvl, L in enumerate(o.levels):
+        S = g.level_stencil(lvl)
+        assert rel(S[1:-1], L.A[1:-1]) < 1e-13, lvl
+
+
+@pytest.mark.parametrize("n", GRIDS)
+def test_apply(n):
+    rng = np.random.default_rng(1)
+    g, o = make(*n)
+    x = rand_node(rng, *n)
+    y = host(g.apply(dev(x)))
+    ref = apply_elastic(x, 1.0 / n[2], LAM, MU)
+    assert rel(y, ref) < 1e-13
+    assert np.all(y[:, 0] == 0) and np.all(y[:, -1] == 0)
+
+
+@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("level", [0, 1])
+def test_colour_passes(n, level):
+    rng = np.random.default_rng(2)
+    g, o = make(*n)
+    L = o.levels[level]
+    x = rand_node(rng, L.nx, L.ny, L.nz, walls=(level == 0))
+    b = rand_node(rng, L.nx, L.ny, L.nz)
+    xd, bd = dev(x), dev(b)
+    for c in [0, 5, 2, 7, 1, 6, 3, 4]:
+        g.level_colour_pass(level, xd, bd, c)
+        L.colour_pass(x, b, (c & 1, (c >> 1) & 1, (c >> 2) & 1))
+        assert rel(host(xd), x) < 1e-13, c
+
+
+@pytest.mark.parametrize("n", GRIDS)
+def test_residual_restrict_prolong(n):
+    rng = np.random.default_rng(3)
+    g, o = make(*n)
+    for level in range(g.levels - 1):
+        L, Lc = o.levels[level], o.levels[level + 1]
+        x = rand_node(rng, L.nx, L.ny, L.nz, walls=(level == 0))
+        b = rand_node(rng, L.nx, L.ny, L.nz)
+        r = host(g.level_residual(level, dev(x), dev(b)))
+        r_ref = o.residual(x, b, level)
+        assert rel(r[:, 1:-1], r_ref[:, 1:-1]) < 1e-13
+        from oracle.multigrid import prolong, restrict
+        bc = host(g.level_restrict(level, dev(r_ref)))
+        assert rel(bc[:, 1:-1], restrict(r_ref)[:, 1:-1]) < 1e-14
+        ec = rand_node(rng, Lc.nx, Lc.ny, Lc.nz, walls=False)
+        xd = dev(x)
+        g.level_prolong_add(level, xd, dev(ec))
+        assert rel(host(xd), x + prolong(ec)) < 1e-14
+
+
+@pytest.mark.parametrize("n", GRIDS)
+def test_coarse_solve(n):
+    rng = np.random.default_rng(4)
+    g, o = make(*n)
+    L = o.levels[-1]
+    b = rand_node(rng, L.nx, L.ny, L.nz)
+    x = np.zeros_like(b)
+    xd = dev(x)
+    g.coarse_solve(xd, dev(b))
+    o.coarse_solve(x, b)
+    assert rel(host(xd), x) < 1e-12
+
+
+@pytest.mark.parametrize("n", GRIDS)
+def test_vcycle_iterates(n):
+    """GPU iterates after each of the first 5 V-cycles match the oracle's (<= 1e-12)."""
+    rng = np.random.default_rng(5)
+    g, o = make(*n)
+    b = rand_node(rng, *n)
+    x0 = rand_node(rng, *n)
+    for k in range(1, 6):
+        xd = dev(x0)
+        info = g.solve(dev(b), xd, rtol=0.0, max_cycles=k)
+        assert info.cycles == k
+        x_ref, oi = o.solve(b, x0, rtol=0.0, max_cycles=k)
+        assert rel(host(xd), x_ref) < 1e-12, k
+        assert abs(info.rel_res - oi["rel_res"]) <= 1e-9 * oi["rel_res"]
+
+
+def test_solve_config0():
+    """32^3, smoothed random stress RHS (seed 0), FP64 V(2,2) to 1e-10."""
+    n = 32
+    g, o = make(n, n, n)
+    b = div_node(stress_field(n, n, n, 0), 1.0 / n)
+    xd = dev(np.zeros_like(b))
+    info = g.solve(dev(b), xd, rtol=1e-10)
+    x_ref, oi = o.solve(b, np.zeros_like(b), rtol=1e-10)
+    assert info.cycles == oi["cycles"]
+    assert info.rel_res <= 1e-10
+    err = np.linalg.norm(host(xd) - x_ref) / np.linalg.norm(x_ref)
+    assert err <= 1e-9
+    assert np.allclose(info.hist, oi["hist"], rtol=1e-8, atol=0)
+
+
+def test_solve_ragged_dirichlet():
+    rng = np.random.default_rng(6)
+    nx, ny, nz = 40, 24, 32
+    g, o = make(nx, ny, nz)
+    b = rand_node(rng, nx, ny, nz)
+    x0 = np.zeros_like(b)
+    x0[:, 0] = rng.standard_normal((3, ny, nx))
+    x0[:, -1] = rng.standard_normal((3, ny, nx))
+    xd = dev(x0)
+    info = g.solve(dev(b), xd, rtol=1e-10)
+    xr = direct_solve(b, x0, 1.0 / nz, LAM, MU)
+    assert info.converged
+    assert np.linalg.norm(host(xd) - xr) / np.linalg.norm(xr) < 1e-9
+    assert np.array_equal(host(xd)[:, 0], x0[:, 0]) and np.array_equal(host(xd)[:, -1], x0[:, -1])
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (48, 48, 48)])
+def test_fp32_refinement(n):
+    """FP32 V-cycles inside FP64 refinement reach the FP64 residual target and
+    the FP64 solution (reference solved to 1e-13)."""
+    g, o = make(*n, precision="fp32-ir")
+    b = div_node(stress_field(*n, 2), 1.0 / n[2])
+    xd = dev(np.zeros_like(b))
+    info = g.solve(dev(b), xd, rtol=1e-10)
+    assert info.converged and info.rel_res <= 1e-10
+    x_ref, _ = o.solve(b, np.zeros_like(b), rtol=1e-13)
+    err = np.linalg.norm(host(xd) - x_ref) / np.linalg.norm(x_ref)
+    assert err < 1e-8, err
+    # contraction per cycle close to the FP64 cycle's
+    _, oi = o.solve(b, np.zeros_like(b), rtol=1e-10)
+    assert info.cycles <= oi["cycles"] + 2
+
+
+def test_other_colour_order():
+    rng = np.random.default_rng(7)
+    order = [0, 4, 1, 5, 2, 6, 3, 7]
+    g, o = make(32, 32, 32, colour_order=order)
+    b = rand_node(rng, 32, 32, 32)
+    x0 = np.zeros_like(b)
+    xd = dev(x0)
+    g.solve(dev(b), xd, rtol=0.0, max_cycles=3)
+    x_ref, _ = o.solve(b, x0, rtol=0.0, max_cycles=3)
+    assert rel(host(xd), x_ref) < 1e-12
+
+
+def test_edge_cases():
+    from paper_1904_03808_amd._capi import (QS_ERR_NONFINITE, QS_ERR_NOT_CONVERGED)
+    rng = np.random.default_rng(8)
+    n = 16
+    g, o = make(n, n, n)
+    # zero lifted right-hand side: x = 0, no cycle
+    x0 = rand_node(rng, n, n, n, walls=False)
+    xd = dev(x0)
+    info = g.solve(dev(np.zeros_like(x0)), xd, rtol=1e-10)
+    assert info.cycles == 0 and np.abs(host(xd)).max() == 0.0
+    # not converged within max_cycles: last iterate kept, status reported
+    b = rand_node(rng, n, n, n)
+    xd = dev(np.zeros_like(b))
+    info = g.solve(dev(b), xd, rtol=1e-14, max_cycles=2, raise_on_failure=False)
+    assert info.status == QS_ERR_NOT_CONVERGED and info.cycles == 2
+    x_ref, _ = o.solve(b, np.zeros_like(b), rtol=0.0, max_cycles=2)
+    assert rel(host(xd), x_ref) < 1e-12
+    # non-finite data
+    b[0, 3, 2, 1] = np.nan
+    info = g.solve(dev(b), dev(np.zeros_like(b)), rtol=1e-10, raise_on_failure=False)
+    assert info.status == QS_ERR_NONFINITE
+
+
+def test_single_level_direct():
+    """nz <= min_coarse_nz: one level solved by the dense inverse, walls lifted."""
+    rng = np.random.default_rng(9)
+    n = 8
+    g, _ = make(n, n, n)
+    assert g.levels == 1
+    b = rand_node(rng, n, n, n)
+    x0 = np.zeros_like(b)
+    x0[:, 0] = rng.standard_normal((3, n, n))
+    xd = dev(x0)
+    info = g.solve(dev(b), xd, rtol=1e-12)
+    assert info.cycles == 1
+    xr = direct_solve(b, x0, 1.0 / n, LAM, MU)
+    assert rel(host(xd), xr) < 1e-12
