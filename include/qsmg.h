@@ -97,6 +97,10 @@ typedef struct qs_handle qs_handle;
 
 const char* qs_status_string(int status);
 
+/* Text of the last HIP failure seen by this thread (the failing call and the
+ * HIP error string), or "" if none. */
+const char* qs_last_error(void);
+
 /* Bytes of device workspace qs_setup needs for these parameters. */
 qs_status qs_workspace_bytes(const qs_params* p, size_t* bytes);
 

@@ -44,7 +44,8 @@ class QSStzParams(C.Structure):
 class QSError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
-        super().__init__("%s: %s (%d)" % (where, lib().qs_status_string(status).decode(), status))
+        super().__init__("%s: %s (%d) [%s]" % (where, lib().qs_status_string(status).decode(),
+                                               status, lib().qs_last_error().decode()))
 
 
 _P = C.c_void_p
@@ -83,12 +84,17 @@ _lib = None
 def lib() -> C.CDLL:
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime (same soname); loading it first makes
+        # the library bind to that runtime, the one that owns the tensors.
+        import torch  # noqa: F401
         if not os.path.exists(_LIB_PATH):
             raise ImportError("libqsmg.so is not built (run __graft_entry__.build() or "
                               "python paper_1904_03808_amd/build.py): %s" % _LIB_PATH)
         L = C.CDLL(_LIB_PATH)
         L.qs_status_string.restype = C.c_char_p
         L.qs_status_string.argtypes = [_I]
+        L.qs_last_error.restype = C.c_char_p
+        L.qs_last_error.argtypes = []
         for name, args in SIGNATURES.items():
             f = getattr(L, name)
             f.argtypes = args

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -138,13 +139,22 @@ void carve(const qs_params* p, const std::vector<int>& dims, char* base, qs_hand
   *total = (cv.off + 255) & ~static_cast<size_t>(255);
 }
 
-#define QS_HIP(call)                              \
-  do {                                            \
-    if ((call) != hipSuccess) return QS_ERR_HIP;  \
+thread_local char g_last_error[256] = "";
+
+qs_status hip_fail(const char* what, hipError_t e) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
+  return QS_ERR_HIP;
+}
+
+#define QS_HIP(call)                                   \
+  do {                                                 \
+    const hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(#call, e_);  \
   } while (0)
 
 qs_status launch_check() {
-  return hipGetLastError() == hipSuccess ? QS_OK : QS_ERR_HIP;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QS_OK : hip_fail("kernel launch", e);
 }
 
 // Read the reduced double written to hd->dnorm[0].
@@ -251,6 +261,8 @@ double pow2_near(double v) {
 
 extern "C" {
 
+const char* qs_last_error(void) { return g_last_error; }
+
 const char* qs_status_string(int s) {
   switch (s) {
     case QS_OK: return "ok";
@@ -303,9 +315,12 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
   hd->p = *p;
   hd->stream = static_cast<hipStream_t>(stream);
   carve(p, dims, static_cast<char*>(workspace), hd, &need);
-  if (hipHostMalloc(reinterpret_cast<void**>(&hd->pinned), 4 * sizeof(double)) != hipSuccess) {
-    delete hd;
-    return QS_ERR_HIP;
+  {
+    const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&hd->pinned), 4 * sizeof(double));
+    if (e != hipSuccess) {
+      delete hd;
+      return hip_fail("hipHostMalloc", e);
+    }
   }
   const double lam = p->lambda, mu = p->mu, h = p->h;
   hd->fc64.h2 = h * h;
@@ -332,20 +347,26 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
     const std::vector<float>& s32 = stage32.back();
     stage32.emplace_back(hl.dinv.begin(), hl.dinv.end());
     const std::vector<float>& d32 = stage32.back();
-    if (hipMemcpyAsync(lb.S64, hl.stencil.data(), hl.stencil.size() * 8, hipMemcpyHostToDevice,
-                       hd->stream) != hipSuccess ||
-        hipMemcpyAsync(lb.D64, hl.dinv.data(), hl.dinv.size() * 8, hipMemcpyHostToDevice,
-                       hd->stream) != hipSuccess ||
-        hipMemcpyAsync(lb.S32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, hd->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(lb.D32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice, hd->stream) !=
-            hipSuccess)
-      st = QS_ERR_HIP;
+    hipError_t e = hipMemcpyAsync(lb.S64, hl.stencil.data(), hl.stencil.size() * 8,
+                                  hipMemcpyHostToDevice, hd->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(lb.D64, hl.dinv.data(), hl.dinv.size() * 8, hipMemcpyHostToDevice,
+                         hd->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(lb.S32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, hd->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(lb.D32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice, hd->stream);
+    if (e != hipSuccess) st = hip_fail("hipMemcpyAsync (stencil upload)", e);
   }
-  if (st == QS_OK && hipMemcpyAsync(hd->Ainv, H.coarse_inv.data(), H.coarse_inv.size() * 8,
-                                    hipMemcpyHostToDevice, hd->stream) != hipSuccess)
-    st = QS_ERR_HIP;
-  if (hipStreamSynchronize(hd->stream) != hipSuccess) st = QS_ERR_HIP;
+  if (st == QS_OK) {
+    const hipError_t e = hipMemcpyAsync(hd->Ainv, H.coarse_inv.data(), H.coarse_inv.size() * 8,
+                                        hipMemcpyHostToDevice, hd->stream);
+    if (e != hipSuccess) st = hip_fail("hipMemcpyAsync (coarse inverse)", e);
+  }
+  {
+    const hipError_t e = hipStreamSynchronize(hd->stream);
+    if (e != hipSuccess) st = hip_fail("hipStreamSynchronize (setup)", e);
+  }
   if (st != QS_OK) {
     (void)hipHostFree(hd->pinned);
     delete hd;
@@ -536,9 +557,7 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
   st = solve_impl(hd, b, v, rtol, max_cycles, info);
   if (st != QS_OK && st != QS_ERR_NOT_CONVERGED) return st;
   launch_stress_update(sstar, v, sigma, d, hd->p.h, sp->dt, hd->p.lambda, hd->p.mu, hd->stream);
-  if (hipMemcpyAsync(chi, chi1, cells(d) * sizeof(double), hipMemcpyDeviceToDevice, hd->stream) !=
-      hipSuccess)
-    return QS_ERR_HIP;
+  QS_HIP(hipMemcpyAsync(chi, chi1, cells(d) * sizeof(double), hipMemcpyDeviceToDevice, hd->stream));
   const qs_status lc = launch_check();
   return lc != QS_OK ? lc : st;
 }
@@ -628,10 +647,8 @@ qs_status qs_level_stencil(qs_handle* hd, int level, double* out_host) {
   if (!hd || level < 0 || level >= hd->nlev || !out_host) return QS_ERR_ARG;
   const LevelBufs& lb = hd->L[level];
   const size_t n = static_cast<size_t>(lb.d.nz + 1) * kStencil;
-  if (hipMemcpyAsync(out_host, lb.S64, n * sizeof(double), hipMemcpyDeviceToHost, hd->stream) !=
-          hipSuccess ||
-      hipStreamSynchronize(hd->stream) != hipSuccess)
-    return QS_ERR_HIP;
+  QS_HIP(hipMemcpyAsync(out_host, lb.S64, n * sizeof(double), hipMemcpyDeviceToHost, hd->stream));
+  QS_HIP(hipStreamSynchronize(hd->stream));
   return QS_OK;
 }
 

@@ -48,11 +48,11 @@ def random_state(rng, nx, ny, nz):
     return v, sig, chi
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 18)])
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20)])
 def test_stz_step(n):
     rng = np.random.default_rng(0)
     nx, ny, nz = n
-    g = solver(nx, ny, nz, min_coarse_nz=nz)
+    g = solver(nx, ny, nz)
     v, sig, chi = random_state(rng, nx, ny, nz)
     for dt in (0.5, 10.0):
         ss, c1 = g.stz_step(P, dt, dev(v), dev(sig), dev(chi))
@@ -61,11 +61,11 @@ def test_stz_step(n):
         assert rel(host(c1) - chi, rc - chi) < 1e-11
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 18)])
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20)])
 def test_rhs_and_stress_update(n):
     rng = np.random.default_rng(1)
     nx, ny, nz = n
-    g = solver(nx, ny, nz, min_coarse_nz=nz)
+    g = solver(nx, ny, nz)
     s = rng.standard_normal((6, nz, ny, nx))
     v = rng.standard_normal((3, nz + 1, ny, nx))
     b = host(g.rhs(dev(s), 0.7))
