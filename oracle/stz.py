@@ -44,27 +44,29 @@ def deviator(S):
 
 
 def plastic_rate(sbar, chi, p):
-    """Scalar D^pl of Eq. stz_dpl; zero at or below the yield stress."""
-    out = np.zeros(np.broadcast(sbar, chi).shape)
-    act = sbar > p["s_y"]
+    """Scalar D^pl of Eq. stz_dpl; zero at or below the yield stress.
+
+    Complex-safe (the yield test looks at the real part), so that the
+    complex-step method can differentiate it.
+    """
+    sbar = np.asarray(sbar)
+    act = np.real(sbar) > p["s_y"]
     sb = np.where(act, sbar, p["s_y"])
     val = (np.exp(-1.0 / chi) * transition_rate(sb, p) * (1.0 - p["s_y"] / sb) / p["tau0"])
-    out[...] = np.where(act, val, 0.0)
-    return out
+    return np.where(act, val, 0.0 * val)
 
 
-def stz_step(v, sigma, chi, h, dt, lam, mu, p):
-    """Intermediate stress (Eq. sig_star_qs) and the updated chi (Eq. chi_evo).
+def stz_pointwise(L, sigma, chi, dt, lam, mu, p):
+    """The cellwise part of the step: (L, sigma, chi) -> (sigma*, chi').
 
-    v: node velocity at step n (walls included), sigma: Voigt cell stress,
-    chi: cell effective temperature.  Returns (sigma_star, chi_next).
+    L[a, b] = d v_a / d x_b at the cell, sigma in Voigt order.  Implements
+    Eq. sig_star_qs and the forward-Euler step of Eq. chi_evo; complex-safe.
     """
-    L = grad_cell(v, h)
     S = voigt_to_full(sigma)
     S0, sbar = deviator(S)
     Dpl = plastic_rate(sbar, chi, p)
-    safe = np.where(sbar > 0.0, sbar, 1.0)
-    ratio = np.where(Dpl > 0.0, Dpl / safe, 0.0)
+    act = np.real(Dpl) > 0.0
+    ratio = np.where(act, Dpl / np.where(act, sbar, 1.0), 0.0 * Dpl)
     trL = L[0, 0] + L[1, 1] + L[2, 2]
     LS = np.einsum("ab...,bc...->ac...", L, S)
     SLt = np.einsum("ab...,cb...->ac...", S, L)
@@ -73,6 +75,15 @@ def stz_step(v, sigma, chi, h, dt, lam, mu, p):
     # D^pl (tensor) : sigma_0 = (D^pl / sbar) sigma_0 : sigma_0 = 2 sbar D^pl
     chi_next = chi + (dt / p["c0"]) * (2.0 * sbar * Dpl / p["s_y"]) * (p["chi_inf"] - chi)
     return full_to_voigt(Sstar), chi_next
+
+
+def stz_step(v, sigma, chi, h, dt, lam, mu, p):
+    """Intermediate stress (Eq. sig_star_qs) and the updated chi (Eq. chi_evo).
+
+    v: node velocity at step n (walls included), sigma: Voigt cell stress,
+    chi: cell effective temperature.  Returns (sigma_star, chi_next).
+    """
+    return stz_pointwise(grad_cell(v, h), sigma, chi, dt, lam, mu, p)
 
 
 def rhs(sigma_star, h, dt):
