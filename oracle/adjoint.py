@@ -105,20 +105,25 @@ def mid_shear_loss_grad(sigma: np.ndarray) -> np.ndarray:
     return g
 
 
-def rollout(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol=1e-13):
-    """nsteps projection steps; returns the final state and per-step checkpoints."""
+def rollout(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol=1e-13, max_cycles=200):
+    """nsteps projection steps; returns the final state and per-step checkpoints.
+
+    rtol <= 0 runs every solve for exactly max_cycles cycles.
+    """
     v, s, c = v0.copy(), s0.copy(), chi0.copy()
     ckpt = []
     for _ in range(nsteps):
         ckpt.append((v, s, c))
         v, s, c, _ = projection_step(v, s, c, h, dt, lam, mu, p, U, solver, rtol=rtol,
-                                     max_cycles=200)
+                                     max_cycles=max_cycles)
     return (v, s, c), ckpt
 
 
-def rollout_grad_chi0(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol=1e-13):
+def rollout_grad_chi0(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol=1e-13,
+                      max_cycles=200):
     """d(mid_shear_loss(s^N)) / d chi^0 by a reverse sweep over the checkpoints."""
-    (vN, sN, cN), ckpt = rollout(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol)
+    (vN, sN, cN), ckpt = rollout(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol,
+                                 max_cycles)
     g_s = mid_shear_loss_grad(sN)
     g_c = np.zeros_like(chi0)
     g_v = np.zeros_like(v0)  # cotangent of v^{n+1} (interior)
@@ -130,7 +135,7 @@ def rollout_grad_chi0(v0, s0, chi0, h, dt, lam, mu, p, U, solver, nsteps, rtol=1
         # v^{n+1}_I = K_II^{-1}(D_h s*/dt - ...): adjoint solve with K^T = K
         g_v[:, 0] = 0.0
         g_v[:, -1] = 0.0
-        lam_v, _ = solver.solve(g_v, np.zeros_like(g_v), rtol=rtol, max_cycles=200)
+        lam_v, _ = solver.solve(g_v, np.zeros_like(g_v), rtol=rtol, max_cycles=max_cycles)
         g_sstar = g_sstar + rhs_vjp(lam_v, h, dt)
         # cellwise STZ map
         L = grad_cell(vn, h)

@@ -1,6 +1,7 @@
 """Differentiable rollout of quasi-static projection steps (torch.autograd).
 
-`ProjectionRollout.apply(chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol)`
+`ProjectionRollout.apply(chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol,
+max_cycles)`
 runs `nsteps` projection steps on the GPU (qs_projection_step) and returns
 the final (sigma, chi, v).  The forward pass keeps one checkpoint (v^n,
 sigma^n, chi^n) per step; the backward pass walks the steps in reverse with
@@ -13,7 +14,10 @@ the library's hand-written adjoint kernels:
 
 Gradients are returned for chi0, sigma0 and the interior of v0 (its wall
 planes are boundary data).  The plastic rate has a kink at sbar = s_Y; the
-derivative of the elastic branch is used there.
+derivative of the elastic branch is used there.  rtol <= 0 runs every solve
+(forward and adjoint) for exactly max_cycles V-cycles, which makes the
+discrete map a smooth function of its inputs (useful for finite-difference
+checks, where a residual-based stop adds noise of order cond(K) * rtol).
 """
 from __future__ import annotations
 
@@ -22,14 +26,15 @@ import torch
 
 class ProjectionRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol):
+    def forward(ctx, chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol, max_cycles=200):
         v, s, c = v0.detach().clone(), sigma0.detach().clone(), chi0.detach().clone()
         ckpt = []
         for _ in range(nsteps):
             ckpt.append((v.clone(), s.clone(), c.clone()))
-            solver.projection_step(params, dt, U, v, s, c, rtol=rtol, max_cycles=200)
+            solver.projection_step(params, dt, U, v, s, c, rtol=rtol, max_cycles=max_cycles)
         ctx.ckpt = ckpt
         ctx.solver, ctx.params, ctx.dt, ctx.rtol = solver, params, dt, rtol
+        ctx.max_cycles = max_cycles
         return s, c, v
 
     @staticmethod
@@ -47,12 +52,12 @@ class ProjectionRollout(torch.autograd.Function):
             g_v[:, 0].zero_()
             g_v[:, -1].zero_()
             lam_v = torch.zeros_like(g_v)
-            solver.solve(g_v, lam_v, rtol=rtol, max_cycles=200)
+            solver.solve(g_v, lam_v, rtol=rtol, max_cycles=ctx.max_cycles)
             solver.rhs_vjp(lam_v, dt, g_sstar)
             g_v = torch.zeros_like(g_v)
             g_s, g_c = solver.stz_step_vjp(params, dt, vn, sn, cn, g_sstar, g_c, g_v)
         ctx.ckpt = None
-        return g_c, g_v, g_s, None, None, None, None, None, None
+        return g_c, g_v, g_s, None, None, None, None, None, None, None
 
 
 def mid_shear_loss(sigma: torch.Tensor) -> torch.Tensor:
@@ -62,6 +67,7 @@ def mid_shear_loss(sigma: torch.Tensor) -> torch.Tensor:
     return (s * s).mean()
 
 
-def rollout_loss(chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol=1e-12):
-    s, c, v = ProjectionRollout.apply(chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol)
+def rollout_loss(chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol=1e-12, max_cycles=200):
+    s, c, v = ProjectionRollout.apply(chi0, v0, sigma0, solver, params, dt, U, nsteps, rtol,
+                                      max_cycles)
     return mid_shear_loss(s)

@@ -101,25 +101,33 @@ def test_adjoint_config_96_finite_differences_and_oracle():
     st, dt, U, steps = _config4(n)
     g = solver(n)
     v0, s0, c0 = dev(st["v"]), dev(st["sigma"]), dev(st["chi"])
+    # fixed 40-cycle solves (converged to rounding): a residual-based stop
+    # would add noise of order cond(K) * rtol to every finite difference
     chi = c0.clone().requires_grad_(True)
-    loss = rollout_loss(chi, v0, s0, g, P, dt, U, steps, rtol=1e-13)
+    loss = rollout_loss(chi, v0, s0, g, P, dt, U, steps, rtol=0.0, max_cycles=40)
     loss.backward()
     grad = host(chi.grad)
 
     def L(c):
         with torch.no_grad():
-            return rollout_loss(c, v0, s0, g, P, dt, U, steps, rtol=1e-13).item()
+            return rollout_loss(c, v0, s0, g, P, dt, U, steps, rtol=0.0, max_cycles=40).item()
 
+    # The map is only piecewise smooth: about 1e-5 of the cells cross the yield
+    # surface sbar = s_Y during the 10 steps (hot spots of chi overshoot under
+    # forward Euler), so the step must stay below the distance to those kinks.
+    # eps = 1e-8 does; rounding then bounds the difference quotient error by
+    # about 40 u L / eps (u = 1.1e-16).
+    eps = 1e-8
     an, fd = [], []
     for seed in range(100, 116):
         d = np.random.default_rng(seed).standard_normal(grad.shape)
         d /= np.sqrt(np.mean(d * d))
-        eps = 1e-6
         dd = dev(d)
         fd.append((L(c0 + eps * dd) - L(c0 - eps * dd)) / (2 * eps))
         an.append(float(np.sum(grad * d)))
     an, fd = np.array(an), np.array(fd)
-    assert np.all(np.abs(fd - an) <= 1e-5 * np.abs(an)), np.abs(fd - an) / np.abs(an)
+    atol = 40 * 1.1e-16 * loss.item() / eps
+    assert np.all(np.abs(fd - an) <= 1e-5 * np.abs(an) + atol), (np.abs(fd - an), np.abs(an), atol)
     path = os.path.join(GOLDEN, "adjoint96.json")
     if os.path.exists(path):
         ref = json.load(open(path))
