@@ -38,7 +38,18 @@ import scipy.sparse as sp
 from .operators import apply_elastic, assemble_elastic, interior_mask, node_index
 
 OFFSETS = [o for o in itertools.product((-1, 0, 1), repeat=3)]  # (oz, oy, ox)
-DEFAULT_ORDER = [(c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)]  # (i, j, k) parities
+
+
+def colour_parities(c: int):
+    """(i, j, k) parities of colour c = (i&1) + 2(j&1) + 4(k&1)."""
+    return (c & 1, (c >> 1) & 1, (c >> 2) & 1)
+
+
+ASCENDING_ORDER = [colour_parities(c) for c in range(8)]
+# Even rows first (their four colours: even then odd planes, even then odd
+# columns), then odd rows; the default sweep order.
+ROW_ORDER = [colour_parities(c) for c in (0, 1, 4, 5, 2, 3, 6, 7)]
+DEFAULT_ORDER = ROW_ORDER
 
 
 class ShapeError(ValueError):
@@ -292,7 +303,7 @@ class MGOracle:
         self.h, self.lam, self.mu = h, lam, mu
         self.n_pre, self.n_post = n_pre, n_post
         self.order = list(order) if order is not None else list(DEFAULT_ORDER)
-        if sorted(self.order) != sorted(DEFAULT_ORDER):
+        if sorted(self.order) != sorted(ASCENDING_ORDER):
             raise ValueError("order must be a permutation of the 8 parity colours")
         if min(nx, ny, nz) < 2:
             raise ShapeError("grid too small")

@@ -11,7 +11,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libqsmg.so")
 BUILD = os.path.join(PKG, "_build")
 
-HIP_SOURCES = ["kernels_mg.hip", "kernels_stz.hip", "api.hip"]
+HIP_SOURCES = ["kernels_mg.hip", "kernels_sweep.hip", "kernels_resid.hip", "kernels_stz.hip", "api.hip"]
 HOST_SOURCES = ["hierarchy.cpp"]
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -2,6 +2,7 @@
 // loops (paper Sec. 3.6), plus the projection step of Sec. 3.3.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -27,6 +28,9 @@ struct LevelBufs {
   float* x32 = nullptr;
   float* b32 = nullptr;
   float* r32 = nullptr;
+  double* y64 = nullptr;  // second smoother buffer (ping-pong), smoothed levels
+  float* y32 = nullptr;
+  int seg = 16;           // z planes per workgroup of the row sweep
   double* S64 = nullptr;
   double* D64 = nullptr;
   float* S32 = nullptr;
@@ -86,6 +90,8 @@ struct qs_handle {
   int partial_n = 0;
   double* dnorm = nullptr;   // device, 4 doubles
   double* pinned = nullptr;  // host pinned, 4 doubles
+  bool row_sweep = false;    // colour order allows the row-parity sweep kernel
+  size_t lds_limit = 0;      // bytes of LDS a workgroup may use
 };
 
 namespace {
@@ -105,10 +111,14 @@ void carve(const qs_params* p, const std::vector<int>& dims, char* base, qs_hand
         lb.b64 = cv.take<double>(e);
       }
       lb.r64 = cv.take<double>(e);
+      if (l < nlev - 1) lb.y64 = cv.take<double>(e);
     } else {
       lb.x32 = cv.take<float>(e);
       lb.b32 = cv.take<float>(e);
-      if (l < nlev - 1) lb.r32 = cv.take<float>(e);
+      if (l < nlev - 1) {
+        lb.r32 = cv.take<float>(e);
+        lb.y32 = cv.take<float>(e);
+      }
     }
     const size_t planes = static_cast<size_t>(lb.d.nz + 1);
     lb.S64 = cv.take<double>(planes * kStencil);
@@ -174,6 +184,7 @@ struct Prec<double> {
   static double* x(LevelBufs& l) { return l.x64; }
   static double* b(LevelBufs& l) { return l.b64; }
   static double* r(LevelBufs& l) { return l.r64; }
+  static double* y(LevelBufs& l) { return l.y64; }
   static const double* S(LevelBufs& l) { return l.S64; }
   static const double* D(LevelBufs& l) { return l.D64; }
   static const FineCoef<double>& fc(qs_handle* hd) { return hd->fc64; }
@@ -183,6 +194,7 @@ struct Prec<float> {
   static float* x(LevelBufs& l) { return l.x32; }
   static float* b(LevelBufs& l) { return l.b32; }
   static float* r(LevelBufs& l) { return l.r32; }
+  static float* y(LevelBufs& l) { return l.y32; }
   static const float* S(LevelBufs& l) { return l.S32; }
   static const float* D(LevelBufs& l) { return l.D32; }
   static const FineCoef<float>& fc(qs_handle* hd) { return hd->fc32; }
@@ -200,7 +212,9 @@ void colour_pass(qs_handle* hd, int l, T* x, const T* b, int colour) {
 template <typename T>
 void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_interior) {
   LevelBufs& lb = hd->L[l];
-  if (l == 0)
+  if (l == 0 && !zero_interior)
+    launch_residual_fine_zm<T, T>(x, b, r, lb.d, hd->fc64, 1.0, nullptr, hd->stream);
+  else if (l == 0)
     launch_residual_fine<T, T>(x, b, r, lb.d, hd->fc64, 1.0, zero_interior, nullptr, hd->stream);
   else
     launch_residual_gen<T>(x, b, r, lb.d, Prec<T>::S(lb), zero_interior, nullptr, hd->stream);
@@ -220,6 +234,73 @@ void coarse_solve(qs_handle* hd, int l, T* x, const T* b, T* scratch) {
   launch_coarse_solve<T>(hd->Ainv, hd->ncoarse, rhs, x, lb.d, hd->ctin, hd->ctout, hd->stream);
 }
 
+// Copy the two wall planes of x into y (both buffers must carry them).
+template <typename T>
+void copy_walls(const T* x, T* y, Dims d, hipStream_t s) {
+  const size_t P = static_cast<size_t>(d.plane());
+  for (int c = 0; c < 3; ++c) {
+    const size_t o0 = static_cast<size_t>(c) * d.comp();
+    const size_t o1 = o0 + static_cast<size_t>(d.nz) * P;
+    (void)hipMemcpyAsync(y + o0, x + o0, P * sizeof(T), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(y + o1, x + o1, P * sizeof(T), hipMemcpyDeviceToDevice, s);
+  }
+}
+
+template <typename T>
+void zero_walls(T* y, Dims d, hipStream_t s) {
+  const size_t P = static_cast<size_t>(d.plane());
+  for (int c = 0; c < 3; ++c) {
+    launch_fill<T>(y + static_cast<size_t>(c) * d.comp(), P, T(0), s);
+    launch_fill<T>(y + static_cast<size_t>(c) * d.comp() + static_cast<size_t>(d.nz) * P, P, T(0), s);
+  }
+}
+
+template <typename T>
+bool use_row_sweep(qs_handle* hd, int l) {
+  const Dims d = hd->L[l].d;
+  const int threads = d.nx >= 256 ? d.nx : (256 / std::max(d.nx, 1)) * d.nx;
+  // the row sweep pays off on the fine level; coarse levels are small enough
+  // that one launch per colour (data in L2/MALL) is faster
+  return l == 0 && hd->row_sweep && (d.nx % 2 == 0) && (d.ny % 2 == 0) && d.nx >= 4 && d.nx <= 512 &&
+         threads >= 168 &&
+         static_cast<size_t>(sweep_lds_bytes(d, sizeof(T))) <= hd->lds_limit;
+}
+
+// `sweeps` Gauss-Seidel sweeps on level l, in the colour order given at
+// setup (forward) or its reverse.  The row-parity kernel ping-pongs between
+// x and the level's second buffer; an odd sweep count ends with a copy back.
+template <typename T>
+void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse) {
+  if (sweeps <= 0) return;
+  LevelBufs& lb = hd->L[l];
+  const int* ord = hd->p.colour_order;
+  if (!use_row_sweep<T>(hd, l)) {
+    for (int s = 0; s < sweeps; ++s)
+      for (int q = 0; q < 8; ++q) colour_pass<T>(hd, l, x, b, ord[reverse ? 7 - q : q]);
+    return;
+  }
+  // y's wall planes are zero from setup (coarse levels, FP32 corrections) or
+  // hold the Dirichlet data copied once per solve (FP64 fine level)
+  T* y = Prec<T>::y(lb);
+  const bool fine = (l == 0);
+  const FineCoef<T>& cf = Prec<T>::fc(hd);
+  const T* S = Prec<T>::S(lb);
+  const T* D = Prec<T>::D(lb);
+  T* cur = x;
+  T* oth = y;
+  const int rp0 = reverse ? 1 : 0, pf = reverse ? 1 : 0, xf = reverse ? 1 : 0;
+  for (int s = 0; s < sweeps; ++s) {
+    launch_sweep_half<T>(cur, cur, oth, b, lb.d, rp0, pf, xf, cf, S, D, fine, lb.seg, hd->stream);
+    launch_sweep_half<T>(cur, oth, oth, b, lb.d, 1 - rp0, pf, xf, cf, S, D, fine, lb.seg,
+                         hd->stream);
+    T* t = cur;
+    cur = oth;
+    oth = t;
+  }
+  if (cur != x)
+    (void)hipMemcpyAsync(x, cur, lb.d.elems() * sizeof(T), hipMemcpyDeviceToDevice, hd->stream);
+}
+
 template <typename T>
 void vcycle(qs_handle* hd, int l, T* x, const T* b) {
   LevelBufs& lb = hd->L[l];
@@ -227,9 +308,7 @@ void vcycle(qs_handle* hd, int l, T* x, const T* b) {
     coarse_solve<T>(hd, l, x, b, Prec<T>::r(lb));
     return;
   }
-  const int* ord = hd->p.colour_order;
-  for (int s = 0; s < hd->p.n_pre; ++s)
-    for (int q = 0; q < 8; ++q) colour_pass<T>(hd, l, x, b, ord[q]);
+  smooth<T>(hd, l, x, b, hd->p.n_pre, false);
   LevelBufs& cb = hd->L[l + 1];
   T* r = Prec<T>::r(lb);
   residual<T>(hd, l, x, b, r, false);
@@ -237,8 +316,7 @@ void vcycle(qs_handle* hd, int l, T* x, const T* b) {
   launch_fill<T>(Prec<T>::x(cb), cb.d.elems(), T(0), hd->stream);
   vcycle<T>(hd, l + 1, Prec<T>::x(cb), Prec<T>::b(cb));
   launch_prolong_add<T>(x, Prec<T>::x(cb), lb.d, hd->stream);
-  for (int s = 0; s < hd->p.n_post; ++s)
-    for (int q = 7; q >= 0; --q) colour_pass<T>(hd, l, x, b, ord[q]);
+  smooth<T>(hd, l, x, b, hd->p.n_post, true);
 }
 
 // ||b - K x||^2 on level 0 in FP64 (optionally writing the residual, scaled,
@@ -246,8 +324,12 @@ void vcycle(qs_handle* hd, int l, T* x, const T* b) {
 template <typename Tout>
 int residual_norm0(qs_handle* hd, const double* x, const double* b, Tout* r, double scale,
                    bool zero_interior) {
-  const int nb = launch_residual_fine<double, Tout>(x, b, r, hd->L[0].d, hd->fc64, scale,
-                                                    zero_interior, hd->partial, hd->stream);
+  const int nb =
+      zero_interior
+          ? launch_residual_fine<double, Tout>(x, b, r, hd->L[0].d, hd->fc64, scale, true,
+                                               hd->partial, hd->stream)
+          : launch_residual_fine_zm<double, Tout>(x, b, r, hd->L[0].d, hd->fc64, scale,
+                                                  hd->partial, hd->stream);
   launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->stream);
   return nb;
 }
@@ -323,6 +405,18 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
     }
   }
   const double lam = p->lambda, mu = p->mu, h = p->h;
+  {
+    static const int kRowOrder[8] = {0, 1, 4, 5, 2, 3, 6, 7};
+    hd->row_sweep = std::memcmp(p->colour_order, kRowOrder, sizeof(kRowOrder)) == 0;
+    int dev = 0, lds = 65536;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        lds > 0)
+      hd->lds_limit = static_cast<size_t>(lds);
+    else
+      hd->lds_limit = 65536;
+    sweep_set_lds_limit(hd->lds_limit);
+  }
   hd->fc64.h2 = h * h;
   hd->fc64.p = lam + 2.0 * mu;
   hd->fc64.q = mu;
@@ -335,6 +429,18 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
   hd->fc32.m4 = static_cast<float>(hd->fc64.m4);
   hd->fc32.inv_diag = static_cast<float>(hd->fc64.inv_diag);
   hd->fc32.ih2 = static_cast<float>(hd->fc64.ih2);
+  for (int l = 0; l < hd->nlev; ++l) {
+    LevelBufs& lb = hd->L[l];
+    // z planes per workgroup: 16 on large levels, fewer on small ones so
+    // that a half sweep still launches a few hundred workgroups
+    const int rpw = lb.d.nx >= 256 ? 1 : 256 / std::max(lb.d.nx, 1);
+    const int groups = std::max(1, (lb.d.ny / 2 + rpw - 1) / rpw);
+    int seg = 32;
+    while (seg > 4 && groups * ((lb.d.nz - 1 + seg - 1) / seg) < 1024) seg /= 2;
+    lb.seg = seg;
+    if (lb.y64) launch_fill<double>(lb.y64, lb.d.elems(), 0.0, hd->stream);
+    if (lb.y32) launch_fill<float>(lb.y32, lb.d.elems(), 0.0f, hd->stream);
+  }
   // upload stencils (FP64 and their FP32 roundings) and the coarse inverse;
   // the staging vectors live until the synchronisation below
   std::vector<std::vector<float>> stage32;
@@ -387,8 +493,7 @@ qs_status qs_apply(qs_handle* hd, const double* x, double* y) {
   if (!hd || !x || !y || x == y) return QS_ERR_ARG;
   const Dims d = hd->L[0].d;
   // y = -(0 - K x) on the interior, walls zeroed
-  launch_residual_fine<double, double>(x, nullptr, y, d, hd->fc64, -1.0, false, nullptr,
-                                       hd->stream);
+  launch_residual_fine_zm<double, double>(x, nullptr, y, d, hd->fc64, -1.0, nullptr, hd->stream);
   for (int c = 0; c < 3; ++c) {
     launch_fill<double>(y + static_cast<size_t>(c) * d.comp(), d.plane(), 0.0, hd->stream);
     launch_fill<double>(y + static_cast<size_t>(c) * d.comp() + static_cast<size_t>(d.nz) * d.plane(),
@@ -418,6 +523,7 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   }
   const bool fixed = !(rtol > 0.0);
   const bool ir = hd->p.precision == QS_FP32_IR;
+  if (!ir && hd->L[0].y64) copy_walls<double>(x, hd->L[0].y64, d0, hd->stream);
   double scale = pow2_near(std::sqrt(nb2 / nunk));
   double scale_used = scale;
   int cycles = 0;
@@ -631,15 +737,21 @@ qs_status qs_coarse_solve(qs_handle* hd, double* x, const double* b) {
 
 qs_status qs_smooth(qs_handle* hd, int level, void* x, const void* b, int sweeps) {
   if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !b || sweeps < 0) return QS_ERR_ARG;
-  const int* ord = hd->p.colour_order;
-  for (int s = 0; s < sweeps; ++s)
-    for (int q = 0; q < 8; ++q) {
-      if (hd->p.precision == QS_FP32_IR)
-        colour_pass<float>(hd, level, static_cast<float*>(x), static_cast<const float*>(b), ord[q]);
-      else
-        colour_pass<double>(hd, level, static_cast<double*>(x), static_cast<const double*>(b),
-                            ord[q]);
-    }
+  // x may carry any wall data here; the second buffer takes a copy for this
+  // call and gets zero walls back afterwards where the solver relies on them
+  // (coarse levels and FP32 corrections).
+  LevelBufs& lb = hd->L[level];
+  if (hd->p.precision == QS_FP32_IR) {
+    float* xf = static_cast<float*>(x);
+    if (lb.y32) copy_walls<float>(xf, lb.y32, lb.d, hd->stream);
+    smooth<float>(hd, level, xf, static_cast<const float*>(b), sweeps, false);
+    if (lb.y32) zero_walls<float>(lb.y32, lb.d, hd->stream);
+  } else {
+    double* xd = static_cast<double*>(x);
+    if (lb.y64) copy_walls<double>(xd, lb.y64, lb.d, hd->stream);
+    smooth<double>(hd, level, xd, static_cast<const double*>(b), sweeps, false);
+    if (lb.y64 && level > 0) zero_walls<double>(lb.y64, lb.d, hd->stream);
+  }
   return launch_check();
 }
 

@@ -34,6 +34,16 @@ template <typename T>
 void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
                        hipStream_t s);
 
+// Row-parity half sweep (kernels_sweep.hip): updates every node of the rows
+// with parity row_par, reading own rows from own_src, neighbour rows from
+// nbr_src and writing dst.  `fine` selects the fine-operator stencil.
+template <typename T>
+void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
+                       int plane_first, int x_first, const FineCoef<T>& cf, const T* S,
+                       const T* Dinv, bool fine, int seg, hipStream_t s);
+int sweep_lds_bytes(Dims d, int bytes_per_value);
+void sweep_set_lds_limit(size_t bytes);
+
 // r = b - A x on interior nodes (walls of r = 0).  If `zero_interior`, x's
 // interior is treated as 0 (r = b - A_IB x_B).  If `partial` is non-null,
 // per-block sums of r^2 (in double) go to partial[blockIdx].  `r` may be
@@ -45,7 +55,15 @@ int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const Fine
 template <typename T>
 int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool zero_interior,
                         double* partial, hipStream_t s);
-int residual_blocks(Dims d);
+int residual_blocks(Dims d);  // upper bound on the partial sums any residual kernel writes
+
+// Fine-operator residual by z-marching tiles (kernels_resid.hip): same
+// contract as launch_residual_fine with zero_interior = false; b may be null
+// (treated as 0).  Returns the number of partial sums written.
+template <typename Tin, typename Tout>
+int launch_residual_fine_zm(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
+                            double out_scale, double* partial, hipStream_t s);
+int resid_zmarch_blocks(Dims d);
 
 template <typename T>
 void launch_restrict(const T* r, T* bc, Dims fine, hipStream_t s);

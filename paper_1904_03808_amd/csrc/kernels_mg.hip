@@ -101,17 +101,18 @@ __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* 
                                                     int nx, int ny, int nz, ColourRange cr,
                                                     const T* __restrict__ S,
                                                     const T* __restrict__ Dinv) {
+  // blockIdx.y selects the plane, so the plane's stencil is wave-uniform and
+  // is read with scalar loads
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cr.total()) return;
+  if (t >= cr.hx * cr.hy) return;
   const int ii = t % cr.hx;
-  const int rest = t / cr.hx;
-  const int jj = rest % cr.hy;
-  const int kk = rest / cr.hy;
-  const int i = 2 * ii + cr.a, j = 2 * jj + cr.bb, k = cr.kfirst + 2 * kk;
+  const int jj = t / cr.hx;
+  const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
+  const int i = 2 * ii + cr.a, j = 2 * jj + cr.bb;
   const int P = nx * ny, C = (nz + 1) * P;
   const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
   const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-  const T* Sk = S + static_cast<size_t>(k) * 243;
+  const T* Sk = S + static_cast<size_t>(__builtin_amdgcn_readfirstlane(k)) * 243;
   T acc[3];
   const int o = k * P + j * nx + i;
 #pragma unroll
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* 
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[c] -= B[c * 3] * n0 + B[c * 3 + 1] * n1 + B[c * 3 + 2] * n2;
       }
-  const T* Di = Dinv + static_cast<size_t>(k) * 9;
+  const T* Di = Dinv + static_cast<size_t>(__builtin_amdgcn_readfirstlane(k)) * 9;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     x[c * C + o] = Di[c * 3] * acc[0] + Di[c * 3 + 1] * acc[1] + Di[c * 3 + 2] * acc[2];
@@ -223,15 +224,16 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restri
                                                                T* __restrict__ r, int nx, int ny,
                                                                int nz, const T* __restrict__ S,
                                                                double* __restrict__ partial) {
+  // blockIdx.y selects the plane (wave-uniform stencil, scalar loads)
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int total = nx * ny * (nz - 1);
+  const int k = 1 + static_cast<int>(blockIdx.y);
   double sq = 0.0;
-  if (t < total) {
+  if (t < nx * ny) {
     const int P = nx * ny, C = (nz + 1) * P;
-    const int i = t % nx, j = (t / nx) % ny, k = 1 + t / P;
+    const int i = t % nx, j = t / nx;
     const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
     const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-    const T* Sk = S + static_cast<size_t>(k) * 243;
+    const T* Sk = S + static_cast<size_t>(__builtin_amdgcn_readfirstlane(k)) * 243;
     const int o = k * P + j * nx + i;
     T acc[3];
 #pragma unroll
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restri
   }
   if (partial) {
     const double s = block_sum(sq);
-    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -413,11 +415,16 @@ void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T
                        hipStream_t s) {
   const ColourRange cr = colour_range(d, colour);
   if (cr.total() <= 0) return;
-  hipLaunchKernelGGL(k_colour_gen<T>, dim3(blocks_for(cr.total(), 256)), dim3(256), 0, s, x, b,
+  hipLaunchKernelGGL(k_colour_gen<T>, dim3(blocks_for(cr.hx * cr.hy, 256), cr.nk), dim3(256), 0, s, x, b,
                      d.nx, d.ny, d.nz, cr, S, Dinv);
 }
 
-int residual_blocks(Dims d) { return blocks_for(static_cast<long long>(d.nx) * d.ny * (d.nz - 1), kReduceBlock); }
+int residual_blocks(Dims d) {
+  const int flat = blocks_for(static_cast<long long>(d.nx) * d.ny * (d.nz - 1), kReduceBlock);
+  const int planes = blocks_for(static_cast<long long>(d.nx) * d.ny, kReduceBlock) * (d.nz - 1);
+  const int zm = resid_zmarch_blocks(d);
+  return std::max(flat, std::max(planes, zm));
+}
 
 template <typename Tin, typename Tout>
 int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
@@ -442,14 +449,14 @@ int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const Fine
 template <typename T>
 int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool zero_interior,
                         double* partial, hipStream_t s) {
-  const int nb = residual_blocks(d);
+  const dim3 grid(blocks_for(static_cast<long long>(d.nx) * d.ny, kReduceBlock), d.nz - 1);
   if (zero_interior)
-    hipLaunchKernelGGL((k_residual_gen<T, true>), dim3(nb), dim3(kReduceBlock), 0, s, x, b, r, d.nx,
+    hipLaunchKernelGGL((k_residual_gen<T, true>), grid, dim3(kReduceBlock), 0, s, x, b, r, d.nx,
                        d.ny, d.nz, S, partial);
   else
-    hipLaunchKernelGGL((k_residual_gen<T, false>), dim3(nb), dim3(kReduceBlock), 0, s, x, b, r,
+    hipLaunchKernelGGL((k_residual_gen<T, false>), grid, dim3(kReduceBlock), 0, s, x, b, r,
                        d.nx, d.ny, d.nz, S, partial);
-  return nb;
+  return static_cast<int>(grid.x * grid.y);
 }
 
 template <typename T>

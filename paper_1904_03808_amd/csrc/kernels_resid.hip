@@ -1,0 +1,199 @@
+// Fine-level residual r = b - K x by z-marching tiles (gfx950).
+//
+// A workgroup of 64 x 4 threads owns a 64 x 4 column tile and a segment of
+// z planes.  Planes k-1, k, k+1 of the tile plus a one-node halo in x and y
+// sit in an LDS ring of three planes, so each value of x is loaded once per
+// workgroup (the halo columns once more by the neighbouring tile, usually
+// from L2); the next plane is fetched into registers while the current one
+// is computed.  The squared residual is summed per workgroup in double for
+// the convergence test.  Tiles are ordered so that each XCD takes a
+// contiguous block of them (neighbouring tiles share halos through its L2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+
+namespace qs {
+
+namespace {
+
+constexpr int TX = 64, TY = 4, HX = TX + 2, HY = TY + 2, HALO = HX * HY;
+constexpr int SEGZ = 32;
+
+struct ZmArgs {
+  int nx, ny, nz;
+  int ntx, nty, nseg;
+  int real_wgs, grid_per_xcd;
+};
+
+template <typename T>
+__device__ __forceinline__ int slot_idx(int p, int c, int hy, int hx) {
+  return (((p % 3) * 3 + c) * HY + hy) * HX + hx;
+}
+
+template <typename Tin, typename Tout>
+__global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
+                                                     const Tin* __restrict__ b,
+                                                     Tout* __restrict__ r, ZmArgs a,
+                                                     FineCoef<Tin> cf, Tin out_scale,
+                                                     double* __restrict__ partial) {
+  __shared__ Tin ring[3 * 3 * HALO];
+  __shared__ double red[4];
+  const int wg = blockIdx.x;
+  const int L = (wg & 7) * a.grid_per_xcd + (wg >> 3);
+  if (L >= a.real_wgs) return;
+  const int tx = L % a.ntx;
+  const int rest = L / a.ntx;
+  const int ty = rest % a.nty;
+  const int sg = rest / a.nty;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int i0 = tx * TX, j0 = ty * TY;
+  const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool own = (i < nx) && (j < ny);
+  const size_t P = static_cast<size_t>(nx) * ny, C = static_cast<size_t>(nz + 1) * P;
+  const int z0 = 1 + sg * SEGZ, z1 = min(z0 + SEGZ, nz);
+
+  // halo element e of the tile -> global column offset in a plane
+  size_t hoff[2];
+  int hcount = 0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = threadIdx.x + u * 256;
+    if (e < HALO) {
+      const int hy = e / HX, hx = e - hy * HX;
+      int gj = j0 + hy - 1, gi = i0 + hx - 1;
+      gj = ((gj % ny) + ny) % ny;
+      gi = ((gi % nx) + nx) % nx;
+      hoff[u] = static_cast<size_t>(gj) * nx + gi;
+      hcount = u + 1;
+    }
+  }
+  Tin pre[2][3];
+  auto fetch = [&](int p) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (u < hcount)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pre[u][c] = x[c * C + static_cast<size_t>(p) * P + hoff[u]];
+  };
+  auto store = [&](int p) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (u < hcount) {
+        const int e = threadIdx.x + u * 256;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ring[((p % 3) * 3 + c) * HALO + e] = pre[u][c];
+      }
+  };
+  const size_t oown = own ? static_cast<size_t>(j) * nx + i : 0;
+  Tin bc[3] = {Tin(0), Tin(0), Tin(0)}, bn[3] = {Tin(0), Tin(0), Tin(0)};
+  auto fetch_b = [&](int p, Tin out[3]) {
+    if (b && own && p >= 1 && p <= nz - 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) out[c] = b[c * C + static_cast<size_t>(p) * P + oown];
+    }
+  };
+
+  fetch(z0 - 1);
+  store(z0 - 1);
+  fetch(z0);
+  store(z0);
+  fetch(z0 + 1);
+  fetch_b(z0, bc);
+  double sq = 0.0;
+  const Tin diag = Tin(2) * (cf.p + Tin(2) * cf.q);
+  const int hx = lx + 1, hy = ly + 1;
+  for (int p = z0; p < z1; ++p) {
+    store(p + 1);
+    __syncthreads();
+    if (p + 2 <= nz) fetch(p + 2);
+    fetch_b(p + 1, bn);
+    if (own) {
+#define X(c, dz, dy, dx) ring[slot_idx<Tin>(p + (dz), c, hy + (dy), hx + (dx))]
+      const Tin fx0 = X(0, 0, 0, 1) + X(0, 0, 0, -1), fy0 = X(0, 0, 1, 0) + X(0, 0, -1, 0),
+                fz0 = X(0, 1, 0, 0) + X(0, -1, 0, 0);
+      const Tin fx1 = X(1, 0, 0, 1) + X(1, 0, 0, -1), fy1 = X(1, 0, 1, 0) + X(1, 0, -1, 0),
+                fz1 = X(1, 1, 0, 0) + X(1, -1, 0, 0);
+      const Tin fx2 = X(2, 0, 0, 1) + X(2, 0, 0, -1), fy2 = X(2, 0, 1, 0) + X(2, 0, -1, 0),
+                fz2 = X(2, 1, 0, 0) + X(2, -1, 0, 0);
+      // mixed differences f(+,+) - f(+,-) - f(-,+) + f(-,-)
+      const Tin mxy0 = X(0, 0, 1, 1) - X(0, 0, -1, 1) - X(0, 0, 1, -1) + X(0, 0, -1, -1);
+      const Tin mxy1 = X(1, 0, 1, 1) - X(1, 0, -1, 1) - X(1, 0, 1, -1) + X(1, 0, -1, -1);
+      const Tin mxz0 = X(0, 1, 0, 1) - X(0, -1, 0, 1) - X(0, 1, 0, -1) + X(0, -1, 0, -1);
+      const Tin mxz2 = X(2, 1, 0, 1) - X(2, -1, 0, 1) - X(2, 1, 0, -1) + X(2, -1, 0, -1);
+      const Tin myz1 = X(1, 1, 1, 0) - X(1, -1, 1, 0) - X(1, 1, -1, 0) + X(1, -1, -1, 0);
+      const Tin myz2 = X(2, 1, 1, 0) - X(2, -1, 1, 0) - X(2, 1, -1, 0) + X(2, -1, -1, 0);
+      const Tin off0 = cf.p * fx0 + cf.q * (fy0 + fz0) + cf.m4 * (mxy1 + mxz2);
+      const Tin off1 = cf.p * fy1 + cf.q * (fx1 + fz1) + cf.m4 * (mxy0 + myz2);
+      const Tin off2 = cf.p * fz2 + cf.q * (fx2 + fy2) + cf.m4 * (mxz0 + myz1);
+      const Tin r0 = bc[0] - (diag * X(0, 0, 0, 0) - off0) * cf.ih2;
+      const Tin r1 = bc[1] - (diag * X(1, 0, 0, 0) - off1) * cf.ih2;
+      const Tin r2 = bc[2] - (diag * X(2, 0, 0, 0) - off2) * cf.ih2;
+#undef X
+      sq += static_cast<double>(r0) * r0 + static_cast<double>(r1) * r1 + static_cast<double>(r2) * r2;
+      if (r) {
+        const size_t o = static_cast<size_t>(p) * P + oown;
+        r[o] = static_cast<Tout>(r0 * out_scale);
+        r[C + o] = static_cast<Tout>(r1 * out_scale);
+        r[2 * C + o] = static_cast<Tout>(r2 * out_scale);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bc[c] = bn[c];
+    __syncthreads();
+  }
+  if (partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[L] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+ZmArgs zm_args(Dims d) {
+  ZmArgs a;
+  a.nx = d.nx;
+  a.ny = d.ny;
+  a.nz = d.nz;
+  a.ntx = (d.nx + TX - 1) / TX;
+  a.nty = (d.ny + TY - 1) / TY;
+  a.nseg = (d.nz - 1 + SEGZ - 1) / SEGZ;
+  a.real_wgs = a.ntx * a.nty * a.nseg;
+  a.grid_per_xcd = (a.real_wgs + 7) / 8;
+  return a;
+}
+
+}  // namespace
+
+int resid_zmarch_blocks(Dims d) { return zm_args(d).real_wgs; }
+
+template <typename Tin, typename Tout>
+int launch_residual_fine_zm(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
+                            double out_scale, double* partial, hipStream_t s) {
+  FineCoef<Tin> cf;
+  cf.h2 = static_cast<Tin>(c.h2);
+  cf.p = static_cast<Tin>(c.p);
+  cf.q = static_cast<Tin>(c.q);
+  cf.m4 = static_cast<Tin>(c.m4);
+  cf.inv_diag = static_cast<Tin>(c.inv_diag);
+  cf.ih2 = static_cast<Tin>(c.ih2);
+  const ZmArgs a = zm_args(d);
+  hipLaunchKernelGGL((k_residual_zm<Tin, Tout>), dim3(8 * a.grid_per_xcd), dim3(256), 0, s, x, b,
+                     r, a, cf, static_cast<Tin>(out_scale), partial);
+  return a.real_wgs;
+}
+
+template int launch_residual_fine_zm<double, double>(const double*, const double*, double*, Dims,
+                                                     const FineCoef<double>&, double, double*,
+                                                     hipStream_t);
+template int launch_residual_fine_zm<double, float>(const double*, const double*, float*, Dims,
+                                                    const FineCoef<double>&, double, double*,
+                                                    hipStream_t);
+template int launch_residual_fine_zm<float, float>(const float*, const float*, float*, Dims,
+                                                   const FineCoef<double>&, double, double*,
+                                                   hipStream_t);
+
+}  // namespace qs

@@ -54,7 +54,7 @@ class MGSolver:
 
     def __init__(self, nx: int, ny: int, nz: int, h: float, lam: float, mu: float,
                  min_coarse_nz: int = 8, n_pre: int = 2, n_post: int = 2,
-                 precision: str = "fp64", colour_order: Sequence[int] = tuple(range(8)),
+                 precision: str = "fp64", colour_order: Sequence[int] = (0, 1, 4, 5, 2, 3, 6, 7),
                  device: str | torch.device = "cuda"):
         self.nx, self.ny, self.nz, self.h = nx, ny, nz, h
         self.lam, self.mu = lam, mu
