@@ -65,6 +65,34 @@ def cpu_baseline(n_full: int, cycles_full: int) -> dict:
             "host_cpus": os.cpu_count()}
 
 
+def profile_smoother(n: int) -> None:
+    """Kernels for hardware-counter runs: one device-to-device copy of a known
+    size (calibrates FETCH_SIZE / WRITE_SIZE), then 3 fine-level sweeps in FP32
+    and in FP64 (6 half-sweep launches each) on the 256^3 bench input."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, stress_field
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)  # 512 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    sig = torch.from_numpy(stress_field(n, n, n, 2)).to(dev)
+    for prec, dt_ in (("fp32-ir", torch.float32), ("fp64", torch.float64)):
+        g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp64", device=dev)
+        b = g.rhs(sig, 1.0)
+        g.close()
+        g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision=prec, device=dev)
+        xs = torch.zeros(g.node_shape(0), dtype=dt_, device=dev)
+        g.smooth(0, xs, b.to(dt_), 3)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": prec, "sweeps": 3, "copy_bytes": 512 * 1024 * 1024}),
+              flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +100,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-smoother", action="store_true",
+                    help="only run a calibration copy and fine-level sweeps (for rocprofv3 counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -84,6 +114,9 @@ def main():
     from paper_1904_03808_amd.qsmg import MGSolver
     from workloads import lame, stress_field
 
+    if args.profile_smoother:
+        profile_smoother(args.n)
+        return
     n = args.n
     h = 1.0 / n
     lam, mu = lame()

@@ -263,7 +263,7 @@ bool use_row_sweep(qs_handle* hd, int l) {
   // that one launch per colour (data in L2/MALL) is faster
   return l == 0 && hd->row_sweep && (d.nx % 2 == 0) && (d.ny % 2 == 0) && d.nx >= 4 && d.nx <= 512 &&
          threads >= 168 &&
-         static_cast<size_t>(sweep_lds_bytes(d, sizeof(T))) <= hd->lds_limit;
+         static_cast<size_t>(sweep_lds_bytes(d, sizeof(T), l == 0)) <= hd->lds_limit;
 }
 
 // `sweeps` Gauss-Seidel sweeps on level l, in the colour order given at

@@ -41,7 +41,7 @@ template <typename T>
 void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
                        int plane_first, int x_first, const FineCoef<T>& cf, const T* S,
                        const T* Dinv, bool fine, int seg, hipStream_t s);
-int sweep_lds_bytes(Dims d, int bytes_per_value);
+int sweep_lds_bytes(Dims d, int bytes_per_value, bool fine);
 void sweep_set_lds_limit(size_t bytes);
 
 // r = b - A x on interior nodes (walls of r = 0).  If `zero_interior`, x's

@@ -105,11 +105,16 @@ __global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
   double sq = 0.0;
   const Tin diag = Tin(2) * (cf.p + Tin(2) * cf.q);
   const int hx = lx + 1, hy = ly + 1;
+  // Memory counters complete in order: drain the prologue loads before the
+  // loop (a wait for them inside it would also wait for the prefetch), and
+  // issue b of the next plane before the prefetch of plane p + 2, so that
+  // handing b over at the end of an iteration leaves the prefetch in flight.
+  __builtin_amdgcn_s_waitcnt(0);
   for (int p = z0; p < z1; ++p) {
     store(p + 1);
     __syncthreads();
-    if (p + 2 <= nz) fetch(p + 2);
     fetch_b(p + 1, bn);
+    if (p + 2 <= nz) fetch(p + 2);
     if (own) {
 #define X(c, dz, dy, dx) ring[slot_idx<Tin>(p + (dz), c, hy + (dy), hx + (dx))]
       const Tin fx0 = X(0, 0, 0, 1) + X(0, 0, 0, -1), fy0 = X(0, 0, 1, 0) + X(0, 0, -1, 0),

@@ -300,6 +300,11 @@ __global__ __launch_bounds__(512) void k_sweep_rows(const T* __restrict__ own_sr
     store_coef<T>(coef, cv);
   }
   __syncthreads();
+  // Drain the prologue loads here.  Memory counters complete in order, so a
+  // wait for a prologue load that the compiler would otherwise place inside
+  // the loop (it cannot tell iterations apart) would also wait for every
+  // prefetch issued in that iteration.
+  __builtin_amdgcn_s_waitcnt(0);
   PlaneRegs<T> pa, pb;
   int set = 0;
   for (int f = f0; f <= flast; f += 2) {
@@ -346,9 +351,11 @@ __global__ __launch_bounds__(512) void k_sweep_rows(const T* __restrict__ own_sr
 
 }  // namespace
 
-int sweep_lds_bytes(Dims d, int bytes_per_value) {
+int sweep_lds_bytes(Dims d, int bytes_per_value, bool fine) {
+  // ring of four planes x rows x 3 rows x 3 components; the generic stencil
+  // adds two double-buffered coefficient sets of two planes each
   const int rpw = d.nx >= 256 ? 1 : 256 / d.nx;
-  return (4 * rpw * 9 * d.nx + 4 * kCoef) * bytes_per_value;
+  return (4 * rpw * 9 * d.nx + (fine ? 0 : 4 * kCoef)) * bytes_per_value;
 }
 
 template <typename T>
@@ -370,7 +377,7 @@ void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, D
   a.real_wgs = a.ngroups * a.nseg;
   a.grid_per_xcd = (a.real_wgs + 7) / 8;
   const int threads = a.rows_per_wg * d.nx;
-  const size_t lds = static_cast<size_t>(sweep_lds_bytes(d, sizeof(T)));
+  const size_t lds = static_cast<size_t>(sweep_lds_bytes(d, sizeof(T), fine));
   if (fine)
     hipLaunchKernelGGL((k_sweep_rows<T, true>), dim3(8 * a.grid_per_xcd), dim3(threads), lds, s,
                        own_src, nbr_src, dst, b, a, cf, S, Dinv);
