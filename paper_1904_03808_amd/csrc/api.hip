@@ -30,7 +30,7 @@ struct LevelBufs {
   float* r32 = nullptr;
   double* y64 = nullptr;  // second smoother buffer (ping-pong), smoothed levels
   float* y32 = nullptr;
-  int seg = 16;           // z planes per workgroup of the row sweep
+  int seg64 = 16, seg32 = 16;  // z planes per workgroup of the row sweep (fine level)
   double* S64 = nullptr;
   double* D64 = nullptr;
   float* S32 = nullptr;
@@ -188,6 +188,7 @@ struct Prec<double> {
   static const double* S(LevelBufs& l) { return l.S64; }
   static const double* D(LevelBufs& l) { return l.D64; }
   static const FineCoef<double>& fc(qs_handle* hd) { return hd->fc64; }
+  static int seg(const LevelBufs& l) { return l.seg64; }
 };
 template <>
 struct Prec<float> {
@@ -198,6 +199,7 @@ struct Prec<float> {
   static const float* S(LevelBufs& l) { return l.S32; }
   static const float* D(LevelBufs& l) { return l.D32; }
   static const FineCoef<float>& fc(qs_handle* hd) { return hd->fc32; }
+  static int seg(const LevelBufs& l) { return l.seg32; }
 };
 
 template <typename T>
@@ -257,13 +259,9 @@ void zero_walls(T* y, Dims d, hipStream_t s) {
 
 template <typename T>
 bool use_row_sweep(qs_handle* hd, int l) {
-  const Dims d = hd->L[l].d;
-  const int threads = d.nx >= 256 ? d.nx : (256 / std::max(d.nx, 1)) * d.nx;
   // the row sweep pays off on the fine level; coarse levels are small enough
   // that one launch per colour (data in L2/MALL) is faster
-  return l == 0 && hd->row_sweep && (d.nx % 2 == 0) && (d.ny % 2 == 0) && d.nx >= 4 && d.nx <= 512 &&
-         threads >= 168 &&
-         static_cast<size_t>(sweep_lds_bytes(d, sizeof(T), l == 0)) <= hd->lds_limit;
+  return l == 0 && hd->row_sweep && sweep_supported(hd->L[l].d, hd->lds_limit, sizeof(T));
 }
 
 // `sweeps` Gauss-Seidel sweeps on level l, in the colour order given at
@@ -282,16 +280,13 @@ void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse) {
   // y's wall planes are zero from setup (coarse levels, FP32 corrections) or
   // hold the Dirichlet data copied once per solve (FP64 fine level)
   T* y = Prec<T>::y(lb);
-  const bool fine = (l == 0);
   const FineCoef<T>& cf = Prec<T>::fc(hd);
-  const T* S = Prec<T>::S(lb);
-  const T* D = Prec<T>::D(lb);
   T* cur = x;
   T* oth = y;
   const int rp0 = reverse ? 1 : 0, pf = reverse ? 1 : 0, xf = reverse ? 1 : 0;
   for (int s = 0; s < sweeps; ++s) {
-    launch_sweep_half<T>(cur, cur, oth, b, lb.d, rp0, pf, xf, cf, S, D, fine, lb.seg, hd->stream);
-    launch_sweep_half<T>(cur, oth, oth, b, lb.d, 1 - rp0, pf, xf, cf, S, D, fine, lb.seg,
+    launch_sweep_half<T>(cur, cur, oth, b, lb.d, rp0, pf, xf, cf, Prec<T>::seg(lb), 1, hd->stream);
+    launch_sweep_half<T>(cur, oth, oth, b, lb.d, 1 - rp0, pf, xf, cf, Prec<T>::seg(lb), 1,
                          hd->stream);
     T* t = cur;
     cur = oth;
@@ -431,13 +426,10 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
   hd->fc32.ih2 = static_cast<float>(hd->fc64.ih2);
   for (int l = 0; l < hd->nlev; ++l) {
     LevelBufs& lb = hd->L[l];
-    // z planes per workgroup: 16 on large levels, fewer on small ones so
-    // that a half sweep still launches a few hundred workgroups
-    const int rpw = lb.d.nx >= 256 ? 1 : 256 / std::max(lb.d.nx, 1);
-    const int groups = std::max(1, (lb.d.ny / 2 + rpw - 1) / rpw);
-    int seg = 32;
-    while (seg > 4 && groups * ((lb.d.nz - 1 + seg - 1) / seg) < 1024) seg /= 2;
-    lb.seg = seg;
+    if (l == 0 && sweep_supported(lb.d, hd->lds_limit, 4)) {
+      lb.seg32 = sweep_segment_length(lb.d, 4);
+      if (sweep_supported(lb.d, hd->lds_limit, 8)) lb.seg64 = sweep_segment_length(lb.d, 8);
+    }
     if (lb.y64) launch_fill<double>(lb.y64, lb.d.elems(), 0.0, hd->stream);
     if (lb.y32) launch_fill<float>(lb.y32, lb.d.elems(), 0.0f, hd->stream);
   }

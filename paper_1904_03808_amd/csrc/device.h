@@ -34,14 +34,17 @@ template <typename T>
 void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
                        hipStream_t s);
 
-// Row-parity half sweep (kernels_sweep.hip): updates every node of the rows
-// with parity row_par, reading own rows from own_src, neighbour rows from
-// nbr_src and writing dst.  `fine` selects the fine-operator stencil.
+// Fine-level row-parity half sweep (kernels_sweep.hip): updates every node
+// of the rows with parity row_par, reading own rows from own_src, neighbour
+// rows from nbr_src and writing dst.
 template <typename T>
 void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
-                       int plane_first, int x_first, const FineCoef<T>& cf, const T* S,
-                       const T* Dinv, bool fine, int seg, hipStream_t s);
-int sweep_lds_bytes(Dims d, int bytes_per_value, bool fine);
+                       int plane_first, int x_first, const FineCoef<T>& cf, int seg, int seg_major,
+                       hipStream_t s);
+int sweep_rows_per_group(int nx);  // rows of one parity per workgroup
+int sweep_segment_length(Dims d, int bytes_per_value);  // z planes per workgroup
+int sweep_lds_bytes(Dims d, int bytes_per_value);
+bool sweep_supported(Dims d, size_t lds_limit, int bytes_per_value);
 void sweep_set_lds_limit(size_t bytes);
 
 // r = b - A x on interior nodes (walls of r = 0).  If `zero_interior`, x's
