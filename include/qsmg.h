@@ -38,6 +38,11 @@
  *
  * Errors.  Every entry point returns a qs_status; nothing is thrown and the
  * process is never aborted.  On QS_ERR_HIP the stream may hold partial work.
+ *
+ * Alignment.  Node vectors handed to qs_mg_solve (b, x), qs_projection_step
+ * (v), qs_smooth (x, b), qs_level_restrict (r) and qs_level_prolong_add (x)
+ * must be 16-byte aligned, as every device allocation is (an offset view may
+ * not be); otherwise those entry points return QS_ERR_ARG.
  */
 #ifndef QSMG_H
 #define QSMG_H

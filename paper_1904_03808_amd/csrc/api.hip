@@ -562,9 +562,14 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   return launch_check();
 }
 
+// Kernels that move column pairs as one two-wide access need 16-byte aligned
+// node vectors (every device allocation is; an offset view may not be).
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol, int max_cycles,
                       qs_solve_info* info) {
-  if (!hd || !b || !x || max_cycles < 0 || b == x) return QS_ERR_ARG;
+  if (!hd || !b || !x || max_cycles < 0 || b == x || !aligned16(b) || !aligned16(x))
+    return QS_ERR_ARG;
   return solve_impl(hd, b, x, rtol, max_cycles, info);
 }
 
@@ -638,7 +643,8 @@ qs_status qs_step_scratch_bytes(qs_handle* hd, size_t* bytes) {
 qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double* v,
                              double* sigma, double* chi, void* scratch, double rtol,
                              int max_cycles, qs_solve_info* info) {
-  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || max_cycles < 0)
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || max_cycles < 0 ||
+      !aligned16(v))
     return QS_ERR_ARG;
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
   const Dims d = hd->L[0].d;
@@ -706,13 +712,15 @@ qs_status qs_level_residual(qs_handle* hd, int level, const double* x, const dou
 }
 
 qs_status qs_level_restrict(qs_handle* hd, int level, const double* r, double* b_coarse) {
-  if (!hd || level < 0 || level >= hd->nlev - 1 || !r || !b_coarse) return QS_ERR_ARG;
+  if (!hd || level < 0 || level >= hd->nlev - 1 || !r || !b_coarse || !aligned16(r))
+    return QS_ERR_ARG;
   launch_restrict<double>(r, b_coarse, hd->L[level].d, hd->stream);
   return launch_check();
 }
 
 qs_status qs_level_prolong_add(qs_handle* hd, int level, double* x, const double* e_coarse) {
-  if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !e_coarse) return QS_ERR_ARG;
+  if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !e_coarse || !aligned16(x))
+    return QS_ERR_ARG;
   launch_prolong_add<double>(x, e_coarse, hd->L[level].d, hd->stream);
   return launch_check();
 }
@@ -728,7 +736,9 @@ qs_status qs_coarse_solve(qs_handle* hd, double* x, const double* b) {
 }
 
 qs_status qs_smooth(qs_handle* hd, int level, void* x, const void* b, int sweeps) {
-  if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !b || sweeps < 0) return QS_ERR_ARG;
+  if (!hd || level < 0 || level >= hd->nlev - 1 || !x || !b || sweeps < 0 || !aligned16(x) ||
+      !aligned16(b))
+    return QS_ERR_ARG;
   // x may carry any wall data here; the second buffer takes a copy for this
   // call and gets zero walls back afterwards where the solver relies on them
   // (coarse levels and FP32 corrections).

@@ -96,42 +96,58 @@ __global__ __launch_bounds__(256) void k_colour_fine(T* __restrict__ x, const T*
 }
 
 // Generic per-plane 27-point block stencil S[k][o][c][d].
+// Plane k's 243 stencil entries followed by its 9 inverse-centre entries,
+// copied into LDS by every thread of the block (one load each, issued before
+// the neighbour loads so that waiting for them does not wait for those).
+template <typename T>
+__device__ __forceinline__ void stage_stencil_inverse(T* sc, const T* __restrict__ S,
+                                                      const T* __restrict__ Dinv, int k) {
+  for (int e = threadIdx.x; e < 252; e += blockDim.x)
+    sc[e] = e < 243 ? S[static_cast<size_t>(k) * 243 + e] : Dinv[static_cast<size_t>(k) * 9 + e - 243];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* __restrict__ b,
                                                     int nx, int ny, int nz, ColourRange cr,
                                                     const T* __restrict__ S,
                                                     const T* __restrict__ Dinv) {
-  // blockIdx.y selects the plane, so the plane's stencil is wave-uniform and
-  // is read with scalar loads
+  // blockIdx.y selects the plane; its stencil is staged in LDS and read as
+  // broadcasts.  All 26 neighbour blocks are loaded before any arithmetic, so
+  // each thread waits for one round of memory latency, not one per neighbour.
+  __shared__ T sc[252];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cr.hx * cr.hy) return;
-  const int ii = t % cr.hx;
-  const int jj = t / cr.hx;
+  const bool active = t < cr.hx * cr.hy;
+  const int tt = active ? t : 0;
+  const int ii = tt % cr.hx;
+  const int jj = tt / cr.hx;
   const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
+  stage_stencil_inverse<T>(sc, S, Dinv, k);
   const int i = 2 * ii + cr.a, j = 2 * jj + cr.bb;
   const int P = nx * ny, C = (nz + 1) * P;
   const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
   const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-  const T* Sk = S + static_cast<size_t>(__builtin_amdgcn_readfirstlane(k)) * 243;
-  T acc[3];
   const int o = k * P + j * nx + i;
+  // neighbour n = 0..25 is stencil offset q = n + (n >= 13): the centre is skipped
+  T acc[3], nb[26][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
 #pragma unroll
-  for (int oz = 0; oz < 3; ++oz)
+  for (int n = 0; n < 26; ++n) {
+    const int q = n + (n >= 13 ? 1 : 0);
+    const int off = (k + q / 9 - 1) * P + ys[(q / 3) % 3] * nx + xs[q % 3];
 #pragma unroll
-    for (int oy = 0; oy < 3; ++oy)
+    for (int c = 0; c < 3; ++c) nb[n][c] = x[c * C + off];
+  }
+  __syncthreads();
+  if (!active) return;
 #pragma unroll
-      for (int ox = 0; ox < 3; ++ox) {
-        const int q = oz * 9 + oy * 3 + ox;
-        if (q == 13) continue;
-        const int off = (k + oz - 1) * P + ys[oy] * nx + xs[ox];
-        const T n0 = x[off], n1 = x[C + off], n2 = x[2 * C + off];
-        const T* B = Sk + q * 9;
+  for (int n = 0; n < 26; ++n) {
+    const T* B = sc + (n + (n >= 13 ? 1 : 0)) * 9;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) acc[c] -= B[c * 3] * n0 + B[c * 3 + 1] * n1 + B[c * 3 + 2] * n2;
-      }
-  const T* Di = Dinv + static_cast<size_t>(__builtin_amdgcn_readfirstlane(k)) * 9;
+    for (int c = 0; c < 3; ++c)
+      acc[c] -= B[c * 3] * nb[n][0] + B[c * 3 + 1] * nb[n][1] + B[c * 3 + 2] * nb[n][2];
+  }
+  const T* Di = sc + 243;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     x[c * C + o] = Di[c * 3] * acc[0] + Di[c * 3 + 1] * acc[1] + Di[c * 3 + 2] * acc[2];
@@ -267,18 +283,36 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restri
   }
 }
 
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+
 // b_c(I) = sum over the 27 fine nodes around 2I of w * r(f), w = prod (1 or 1/2).
+// One thread per coarse node; per fine row it loads the pair (2I, 2I+1) as one
+// two-wide access and takes 2I-1 from the lane to its left (a separate load
+// only on the first lane of a wave or of a row).
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __restrict__ bc,
                                                   int nxf, int nyf, int nzf) {
+  using V = typename Pair<T>::type;
   const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = nxc * nyc * (nzc - 1);
-  if (t >= total) return;
-  const int I = t % nxc, J = (t / nxc) % nyc, K = 1 + t / (nxc * nyc);
+  if (total <= 0) return;
+  const bool act = t < total;
+  const int tt = act ? t : total - 1;  // lanes past the end still take part in the shuffles
+  const int I = tt % nxc, J = (tt / nxc) % nyc, K = 1 + tt / (nxc * nyc);
+  const bool own_left = (threadIdx.x & 63) == 0 || I == 0;
+  const int il = I == 0 ? nxf - 1 : 2 * I - 1;
   const int Pf = nxf * nyf, Cf = (nzf + 1) * Pf;
   const int Pc = nxc * nyc, Cc = (nzc + 1) * Pc;
-  const int xs[3] = {wrap_m(2 * I, nxf), 2 * I, 2 * I + 1};
   const int ys[3] = {wrap_m(2 * J, nyf), 2 * J, 2 * J + 1};
   const T w[3] = {T(0.5), T(1), T(0.5)};
 #pragma unroll
@@ -291,43 +325,57 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
         const T* row = r + c * Cf + kf * Pf + ys[dy] * nxf;
-        const T ax = T(0.5) * row[xs[0]] + row[xs[1]] + T(0.5) * row[xs[2]];
+        const V v = *reinterpret_cast<const V*>(row + 2 * I);
+        T left = __shfl_up(v.y, 1, 64);
+        if (own_left) left = row[il];
+        const T ax = T(0.5) * left + v.x + T(0.5) * v.y;
         az += w[dy] * ax;
       }
       acc += w[dz] * az;
     }
-    bc[c * Cc + K * Pc + J * nxc + I] = acc;
+    if (act) bc[c * Cc + K * Pc + J * nxc + I] = acc;
   }
 }
 
-// x(f) += sum_J w(f - 2J) e(J) over the (up to 8) coarse nodes around f.
+// x(f) += sum_J w(f - 2J) e(J) over the (up to 8) coarse nodes around f.  One
+// thread per pair of fine columns (2I, 2I+1) of a row, which use the coarse
+// columns I and I+1; the pair is read and written as one two-wide access.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T* __restrict__ ec,
                                                      int nxf, int nyf, int nzf) {
+  using V = typename Pair<T>::type;
   const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int total = nxf * nyf * (nzf - 1);
+  const int total = nxc * nyf * (nzf - 1);
   if (t >= total) return;
-  const int i = t % nxf, j = (t / nxf) % nyf, k = 1 + t / (nxf * nyf);
+  const int i0 = t % nxc, j = (t / nxc) % nyf, k = 1 + t / (nxc * nyf);
   const int Pf = nxf * nyf, Cf = (nzf + 1) * Pf;
   const int Pc = nxc * nyc, Cc = (nzc + 1) * Pc;
-  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const int i1 = (i & 1) ? (i0 + 1 == nxc ? 0 : i0 + 1) : i0;
+  const int i1 = i0 + 1 == nxc ? 0 : i0 + 1;
+  const int j0 = j >> 1, k0 = k >> 1;
   const int j1 = (j & 1) ? (j0 + 1 == nyc ? 0 : j0 + 1) : j0;
   const int k1 = (k & 1) ? k0 + 1 : k0;
-  const T wx = (i & 1) ? T(0.5) : T(1), wy = (j & 1) ? T(0.5) : T(1), wz = (k & 1) ? T(0.5) : T(1);
-  // with an even index both "neighbours" coincide and carry weight 1 once
-  const bool ox = i & 1, oy = j & 1, oz = k & 1;
+  const bool oy = j & 1, oz = k & 1;
+  const T wy = oy ? T(0.5) : T(1), wz = oz ? T(0.5) : T(1);
+  const size_t o = static_cast<size_t>(k) * Pf + static_cast<size_t>(j) * nxf + 2 * i0;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const T* E = ec + c * Cc;
-    auto row = [&](int kk, int jj) {
+    // even fine column: e(i0); odd fine column: (e(i0) + e(i1)) / 2
+    auto row_e = [&](int kk, int jj) { return E[kk * Pc + jj * nxc + i0]; };
+    auto row_o = [&](int kk, int jj) {
       const T* p = E + kk * Pc + jj * nxc;
-      return ox ? wx * (p[i0] + p[i1]) : p[i0];
+      return T(0.5) * (p[i0] + p[i1]);
     };
-    auto plane = [&](int kk) { return oy ? wy * (row(kk, j0) + row(kk, j1)) : row(kk, j0); };
-    const T add = oz ? wz * (plane(k0) + plane(k1)) : plane(k0);
-    x[c * Cf + k * Pf + j * nxf + i] += add;
+    auto plane_e = [&](int kk) { return oy ? wy * (row_e(kk, j0) + row_e(kk, j1)) : row_e(kk, j0); };
+    auto plane_o = [&](int kk) { return oy ? wy * (row_o(kk, j0) + row_o(kk, j1)) : row_o(kk, j0); };
+    const T add_e = oz ? wz * (plane_e(k0) + plane_e(k1)) : plane_e(k0);
+    const T add_o = oz ? wz * (plane_o(k0) + plane_o(k1)) : plane_o(k0);
+    V* px = reinterpret_cast<V*>(x + c * Cf + o);
+    V v = *px;
+    v.x += add_e;
+    v.y += add_o;
+    *px = v;
   }
 }
 
@@ -469,7 +517,8 @@ void launch_restrict(const T* r, T* bc, Dims f, hipStream_t s) {
 
 template <typename T>
 void launch_prolong_add(T* x, const T* ec, Dims f, hipStream_t s) {
-  const long long total = static_cast<long long>(f.nx) * f.ny * (f.nz - 1);
+  const long long total = static_cast<long long>(f.nx / 2) * f.ny * (f.nz - 1);
+  if (total <= 0) return;
   hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, ec, f.nx,
                      f.ny, f.nz);
 }

@@ -244,6 +244,14 @@ def test_edge_cases():
     b[0, 3, 2, 1] = np.nan
     info = g.solve(dev(b), dev(np.zeros_like(b)), rtol=1e-10, raise_on_failure=False)
     assert info.status == QS_ERR_NONFINITE
+    # a node vector that is not 16-byte aligned is refused before any launch
+    from paper_1904_03808_amd._capi import QS_ERR_ARG
+    flat = torch.zeros(b.size + 1, dtype=torch.float64, device="cuda")
+    xm = flat[1:].view(b.shape)
+    assert xm.data_ptr() % 16 == 8
+    info = g.solve(dev(np.nan_to_num(b)), xm, rtol=1e-10, raise_on_failure=False)
+    assert info.status == QS_ERR_ARG
+    assert torch.count_nonzero(flat).item() == 0
 
 
 def test_single_level_direct():
