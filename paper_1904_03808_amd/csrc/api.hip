@@ -305,9 +305,13 @@ void vcycle(qs_handle* hd, int l, T* x, const T* b) {
   }
   smooth<T>(hd, l, x, b, hd->p.n_pre, false);
   LevelBufs& cb = hd->L[l + 1];
-  T* r = Prec<T>::r(lb);
-  residual<T>(hd, l, x, b, r, false);
-  launch_restrict<T>(r, Prec<T>::b(cb), lb.d, hd->stream);
+  if (l == 0) {
+    launch_resid_restrict<T>(x, b, Prec<T>::b(cb), lb.d, hd->fc64, hd->stream);
+  } else {
+    T* r = Prec<T>::r(lb);
+    residual<T>(hd, l, x, b, r, false);
+    launch_restrict<T>(r, Prec<T>::b(cb), lb.d, hd->stream);
+  }
   launch_fill<T>(Prec<T>::x(cb), cb.d.elems(), T(0), hd->stream);
   vcycle<T>(hd, l + 1, Prec<T>::x(cb), Prec<T>::b(cb));
   launch_prolong_add<T>(x, Prec<T>::x(cb), lb.d, hd->stream);

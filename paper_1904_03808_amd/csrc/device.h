@@ -67,6 +67,11 @@ template <typename Tin, typename Tout>
 int launch_residual_fine_zm(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
                             double out_scale, double* partial, hipStream_t s);
 int resid_zmarch_blocks(Dims d);
+// Fine level: bc = T^T (b - K x) on the interior coarse nodes, without
+// writing the fine residual (kernels_resid.hip).  nx, ny, nz even.
+template <typename T>
+void launch_resid_restrict(const T* x, const T* b, T* bc, Dims d, const FineCoef<double>& c,
+                           hipStream_t s);
 
 template <typename T>
 void launch_restrict(const T* r, T* bc, Dims fine, hipStream_t s);

@@ -171,6 +171,194 @@ ZmArgs zm_args(Dims d) {
   return a;
 }
 
+// Fused fine residual and restriction, b_c = R (b - K x) with R = T^T: the
+// residual never leaves the chip.  A workgroup owns a 64 x 8 fine tile, i.e.
+// the 32 x 4 coarse nodes at its even positions, over a segment of coarse
+// planes, and marches up the fine planes 2 K0 - 1 .. 2 K1 - 1.  Per fine plane
+// it computes the residual on the 65 x 9 patch those coarse nodes read (one
+// extra column and row below the tile), from x staged in a 3-plane LDS ring
+// with a 67 x 11 footprint, reduces the patch in x and y for each coarse node
+// and adds the result, weighted for the plane's z offset, to the coarse
+// node's running sum, which is written when its third plane is done.  Both the
+// residual and the weighted sums are evaluated in the same order as the
+// separate residual and restriction kernels, so the result is identical.
+constexpr int FX = 64, FY = 8;                      // fine tile
+constexpr int RXN = FX + 1, RYN = FY + 1, RN = RXN * RYN;  // residual patch
+constexpr int XXN = FX + 3, XYN = FY + 3, XN = XXN * XYN;  // x patch
+constexpr int CSEG = 16;                            // coarse planes per segment
+
+struct RrArgs {
+  int nx, ny, nz;
+  int ntx, nty, nseg;
+  int real_wgs, grid_per_xcd;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(const T* __restrict__ x,
+                                                        const T* __restrict__ b,
+                                                        T* __restrict__ bc, RrArgs a,
+                                                        FineCoef<T> cf) {
+  __shared__ T ring[3 * 3 * XN];  // [plane % 3][component][XYN][XXN]
+  __shared__ T rp[3 * RN];        // residual of the current plane [component][RYN][RXN]
+  const int wg = blockIdx.x;
+  const int L = (wg & 7) * a.grid_per_xcd + (wg >> 3);
+  if (L >= a.real_wgs) return;
+  const int tx = L % a.ntx;
+  const int rest = L / a.ntx;
+  const int ty = rest % a.nty;
+  const int sg = rest / a.nty;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int nxc = nx / 2, nyc = ny / 2, nzc = nz / 2;
+  const int i0 = tx * FX, j0 = ty * FY;
+  const int K0 = 1 + sg * CSEG, K1 = min(K0 + CSEG, nzc);  // coarse planes [K0, K1)
+  const size_t P = static_cast<size_t>(nx) * ny, C = static_cast<size_t>(nz + 1) * P;
+  const int tid = threadIdx.x;
+
+  // x patch element e -> offset within a plane (columns i0-2.., rows j0-2..)
+  size_t hoff[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int e = min(tid + u * 256, XN - 1);
+    const int hy = e / XXN, hx = e - hy * XXN;
+    const int gj = (j0 - 2 + hy + 2 * ny) % ny, gi = (i0 - 2 + hx + 2 * nx) % nx;
+    hoff[u] = static_cast<size_t>(gj) * nx + gi;
+  }
+  // residual patch node e -> plane offset and position in the x patch
+  size_t roff[3];
+  int rpos[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int e = min(tid + u * 256, RN - 1);
+    const int ry = e / RXN, rx = e - ry * RXN;
+    const int gj = (j0 - 1 + ry + ny) % ny, gi = (i0 - 1 + rx + nx) % nx;
+    roff[u] = static_cast<size_t>(gj) * nx + gi;
+    rpos[u] = (ry + 1) * XXN + rx + 1;
+  }
+  T pre[3][3];
+  auto fetch = [&](int p) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (tid + u * 256 < XN)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pre[u][c] = x[c * C + static_cast<size_t>(p) * P + hoff[u]];
+  };
+  auto store = [&](int p) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = tid + u * 256;
+      if (e < XN)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ring[((p % 3) * 3 + c) * XN + e] = pre[u][c];
+    }
+  };
+  T bcur[3][3], bnext[3][3];
+  auto fetch_b = [&](int p, T out[3][3]) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (tid + u * 256 < RN)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[u][c] = b[c * C + static_cast<size_t>(p) * P + roff[u]];
+  };
+
+  const int kf0 = 2 * K0 - 1, kf1 = 2 * K1 - 1;  // fine planes of the march
+  fetch(kf0 - 1);
+  store(kf0 - 1);
+  fetch(kf0);
+  store(kf0);
+  fetch_b(kf0, bcur);
+  fetch(kf0 + 1);
+  // drain the prologue loads (memory counters complete in order; a wait for
+  // them placed inside the loop would also wait for each prefetch)
+  __builtin_amdgcn_s_waitcnt(0);
+  const T diag = T(2) * (cf.p + T(2) * cf.q);
+  // coarse node of this thread (threads < 128) and its running sums
+  const int Il = tid & 31, Jl = tid >> 5;
+  const int I = i0 / 2 + Il, J = j0 / 2 + Jl;
+  const bool cown = tid < 128 && I < nxc && J < nyc;
+  T acc[3] = {T(0), T(0), T(0)};
+  for (int kf = kf0; kf <= kf1; ++kf) {
+    store(kf + 1);
+    __syncthreads();
+    if (kf + 1 <= kf1) fetch_b(kf + 1, bnext);
+    if (kf + 2 <= nz) fetch(kf + 2);
+    // residual on the patch
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = tid + u * 256;
+      if (e < RN) {
+        const int pc = kf % 3, pm = (kf + 2) % 3, pp = (kf + 1) % 3;
+        const int q = rpos[u];
+#define X(c, pl, dy, dx) ring[((pl) * 3 + (c)) * XN + q + (dy) * XXN + (dx)]
+        const T fx0 = X(0, pc, 0, 1) + X(0, pc, 0, -1), fy0 = X(0, pc, 1, 0) + X(0, pc, -1, 0),
+                fz0 = X(0, pp, 0, 0) + X(0, pm, 0, 0);
+        const T fx1 = X(1, pc, 0, 1) + X(1, pc, 0, -1), fy1 = X(1, pc, 1, 0) + X(1, pc, -1, 0),
+                fz1 = X(1, pp, 0, 0) + X(1, pm, 0, 0);
+        const T fx2 = X(2, pc, 0, 1) + X(2, pc, 0, -1), fy2 = X(2, pc, 1, 0) + X(2, pc, -1, 0),
+                fz2 = X(2, pp, 0, 0) + X(2, pm, 0, 0);
+        // mixed differences f(+,+) - f(+,-) - f(-,+) + f(-,-)
+        const T mxy0 = X(0, pc, 1, 1) - X(0, pc, -1, 1) - X(0, pc, 1, -1) + X(0, pc, -1, -1);
+        const T mxy1 = X(1, pc, 1, 1) - X(1, pc, -1, 1) - X(1, pc, 1, -1) + X(1, pc, -1, -1);
+        const T mxz0 = X(0, pp, 0, 1) - X(0, pm, 0, 1) - X(0, pp, 0, -1) + X(0, pm, 0, -1);
+        const T mxz2 = X(2, pp, 0, 1) - X(2, pm, 0, 1) - X(2, pp, 0, -1) + X(2, pm, 0, -1);
+        const T myz1 = X(1, pp, 1, 0) - X(1, pm, 1, 0) - X(1, pp, -1, 0) + X(1, pm, -1, 0);
+        const T myz2 = X(2, pp, 1, 0) - X(2, pm, 1, 0) - X(2, pp, -1, 0) + X(2, pm, -1, 0);
+        const T off0 = cf.p * fx0 + cf.q * (fy0 + fz0) + cf.m4 * (mxy1 + mxz2);
+        const T off1 = cf.p * fy1 + cf.q * (fx1 + fz1) + cf.m4 * (mxy0 + myz2);
+        const T off2 = cf.p * fz2 + cf.q * (fx2 + fy2) + cf.m4 * (mxz0 + myz1);
+        rp[e] = bcur[u][0] - (diag * X(0, pc, 0, 0) - off0) * cf.ih2;
+        rp[RN + e] = bcur[u][1] - (diag * X(1, pc, 0, 0) - off1) * cf.ih2;
+        rp[2 * RN + e] = bcur[u][2] - (diag * X(2, pc, 0, 0) - off2) * cf.ih2;
+#undef X
+      }
+    }
+    __syncthreads();
+    if (cown) {
+      // x-y reduction around fine (2 Il, 2 Jl) of the tile = patch (2 Il + 1, 2 Jl + 1)
+      const T w[3] = {T(0.5), T(1), T(0.5)};
+      const bool odd = kf & 1;
+      const int Kdone = (kf - 1) / 2;  // coarse plane completed by an odd fine plane
+      const size_t ob = static_cast<size_t>(J) * nxc + I;
+      const size_t Pc = static_cast<size_t>(nxc) * nyc, Cc = static_cast<size_t>(nzc + 1) * Pc;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        T az = T(0);
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          const T* row = rp + c * RN + (2 * Jl + dy) * RXN + 2 * Il;
+          const T ax = T(0.5) * row[0] + row[1] + T(0.5) * row[2];
+          az += w[dy] * ax;
+        }
+        if (odd) {
+          if (kf > kf0) {
+            acc[c] += w[2] * az;
+            bc[c * Cc + static_cast<size_t>(Kdone) * Pc + ob] = acc[c];
+          }
+          acc[c] = T(0) + w[0] * az;
+        } else {
+          acc[c] += w[1] * az;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bcur[u][c] = bnext[u][c];
+  }
+}
+
+RrArgs rr_args(Dims d) {
+  RrArgs a;
+  a.nx = d.nx;
+  a.ny = d.ny;
+  a.nz = d.nz;
+  a.ntx = (d.nx + FX - 1) / FX;
+  a.nty = (d.ny + FY - 1) / FY;
+  a.nseg = (d.nz / 2 - 1 + CSEG - 1) / CSEG;
+  a.real_wgs = a.ntx * a.nty * a.nseg;
+  a.grid_per_xcd = (a.real_wgs + 7) / 8;
+  return a;
+}
+
 }  // namespace
 
 int resid_zmarch_blocks(Dims d) { return zm_args(d).real_wgs; }
@@ -191,6 +379,26 @@ int launch_residual_fine_zm(const Tin* x, const Tin* b, Tout* r, Dims d, const F
   return a.real_wgs;
 }
 
+template <typename T>
+void launch_resid_restrict(const T* x, const T* b, T* bc, Dims d, const FineCoef<double>& c,
+                           hipStream_t s) {
+  if (d.nz / 2 - 1 <= 0) return;
+  FineCoef<T> cf;
+  cf.h2 = static_cast<T>(c.h2);
+  cf.p = static_cast<T>(c.p);
+  cf.q = static_cast<T>(c.q);
+  cf.m4 = static_cast<T>(c.m4);
+  cf.inv_diag = static_cast<T>(c.inv_diag);
+  cf.ih2 = static_cast<T>(c.ih2);
+  const RrArgs a = rr_args(d);
+  hipLaunchKernelGGL((k_resid_restrict<T>), dim3(8 * a.grid_per_xcd), dim3(256), 0, s, x, b, bc, a,
+                     cf);
+}
+
+template void launch_resid_restrict<double>(const double*, const double*, double*, Dims,
+                                            const FineCoef<double>&, hipStream_t);
+template void launch_resid_restrict<float>(const float*, const float*, float*, Dims,
+                                           const FineCoef<double>&, hipStream_t);
 template int launch_residual_fine_zm<double, double>(const double*, const double*, double*, Dims,
                                                      const FineCoef<double>&, double, double*,
                                                      hipStream_t);
