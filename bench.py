@@ -24,6 +24,23 @@ sys.path.insert(0, ROOT)
 METRIC = "V-cycle solves/s + smoother HBM GB/s, 256^3 to 1e-10 rel resid, FP32-IR vs FP64"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the fine FP32 half sweep at 256^3, from two rocprofv3
+# counter runs of `bench.py --profile-smoother` (FETCH_SIZE, then WRITE_SIZE; KiB
+# per dispatch, mean of 6 launches).  A 512 MiB device copy reads as
+# FETCH_SIZE = 262,166 KiB and WRITE_SIZE = 524,288 KiB: on this chip every read
+# request (TCC_EA0_RDREQ, 4,194,593 for the copy) carries 128 bytes but the
+# derived FETCH_SIZE prices it at 64, so reads scale by 2.0 and writes by 1.0.
+# Valid only for the kernel source these counters were taken on.
+SWEEP_COUNTERS = {
+    "kernel_source": "paper_1904_03808_amd/csrc/kernels_sweep.hip",
+    "source_sha256_16": "a2269d1de944538f",
+    "n": 256,
+    "fetch_kib": 180882.0,
+    "write_kib": 97920.0,
+    "fetch_scale": 2.0,
+    "write_scale": 1.0,
+}
+
 
 def _events_ms(fn, reps: int) -> float:
     import torch
@@ -35,6 +52,18 @@ def _events_ms(fn, reps: int) -> float:
     stop.record()
     stop.synchronize()
     return start.elapsed_time(stop) / reps
+
+
+def sweep_traffic(n: int):
+    """HBM bytes per FP32 fine half-sweep launch from the stored counters, or
+    None when the workload or the kernel source differs from the measured one."""
+    import hashlib
+    sc = SWEEP_COUNTERS
+    with open(os.path.join(ROOT, sc["kernel_source"]), "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()[:16]
+    if h != sc["source_sha256_16"] or n != sc["n"]:
+        return None
+    return 1024.0 * (sc["fetch_kib"] * sc["fetch_scale"] + sc["write_kib"] * sc["write_scale"])
 
 
 def cpu_baseline(n_full: int, cycles_full: int) -> dict:
@@ -128,7 +157,7 @@ def main():
     b = g64.rhs(sig, 1.0)
     del sig
     x = torch.zeros_like(b)
-    nodes = 3 * n * n * (n - 1) // 3  # interior nodes
+    nodes = n * n * (n - 1)  # interior nodes
 
     def run(g):
         x.zero_()
@@ -165,7 +194,11 @@ def main():
                     "avg_launch_us": ms * 1e3 / 2,
                     "effective_GBs": bpn * nodes / (ms * 1e-3) / 1e9}
         del xs, bs
-    achieved = sm["fp32"]["effective_GBs"]
+    # roofline kernel: one FP32 half sweep; algorithmic bytes per launch =
+    # 36 B x (interior nodes / 2), over the average launch time from HIP events
+    algo_bytes = 36.0 * nodes / 2
+    achieved = algo_bytes / (sm["fp32"]["avg_launch_us"] * 1e-6) / 1e9
+    traffic = sweep_traffic(n)
     out = {
         "metric": METRIC,
         "value": results["fp32_ir"]["solves_per_s"],
@@ -191,9 +224,13 @@ def main():
         "fp32ir_vs_fp64_rel_l2": err,
         "smoother": sm,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep_rows<float, fine>: fine-level FP32 half sweep",
-                     "bytes_per_node_update": 36},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep_rows<float, 256>: fine-level FP32 half sweep",
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "bytes_per_node_update": 36,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
+                     "traffic_GBs": (traffic / (sm["fp32"]["avg_launch_us"] * 1e-6) / 1e9
+                                     if traffic else None)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, results["fp64"]["cycles"])
