@@ -112,8 +112,9 @@ __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* 
                                                     const T* __restrict__ S,
                                                     const T* __restrict__ Dinv) {
   // blockIdx.y selects the plane; its stencil is staged in LDS and read as
-  // broadcasts.  All 26 neighbour blocks are loaded before any arithmetic, so
-  // each thread waits for one round of memory latency, not one per neighbour.
+  // broadcasts.  The three neighbour planes are visited in a loop that is not
+  // unrolled; each visit issues its 27 loads together (the centre node's are
+  // unused), so a thread waits for three rounds of memory latency.
   __shared__ T sc[252];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = t < cr.hx * cr.hy;
@@ -127,25 +128,29 @@ __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* 
   const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
   const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
   const int o = k * P + j * nx + i;
-  // neighbour n = 0..25 is stencil offset q = n + (n >= 13): the centre is skipped
-  T acc[3], nb[26][3];
+  T acc[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
-#pragma unroll
-  for (int n = 0; n < 26; ++n) {
-    const int q = n + (n >= 13 ? 1 : 0);
-    const int off = (k + q / 9 - 1) * P + ys[(q / 3) % 3] * nx + xs[q % 3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) nb[n][c] = x[c * C + off];
-  }
   __syncthreads();
   if (!active) return;
+#pragma unroll 1
+  for (int oz = 0; oz < 3; ++oz) {
+    const int kk = k + oz - 1;
+    T nb[9][3];
 #pragma unroll
-  for (int n = 0; n < 26; ++n) {
-    const T* B = sc + (n + (n >= 13 ? 1 : 0)) * 9;
+    for (int q = 0; q < 9; ++q) {
+      const int off = kk * P + ys[q / 3] * nx + xs[q % 3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      acc[c] -= B[c * 3] * nb[n][0] + B[c * 3 + 1] * nb[n][1] + B[c * 3 + 2] * nb[n][2];
+      for (int c = 0; c < 3; ++c) nb[q][c] = x[c * C + off];
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      if (oz == 1 && q == 4) continue;  // centre block
+      const T* B = sc + (oz * 9 + q) * 9;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        acc[c] -= B[c * 3] * nb[q][0] + B[c * 3 + 1] * nb[q][1] + B[c * 3 + 2] * nb[q][2];
+    }
   }
   const T* Di = sc + 243;
 #pragma unroll
@@ -240,37 +245,46 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restri
                                                                T* __restrict__ r, int nx, int ny,
                                                                int nz, const T* __restrict__ S,
                                                                double* __restrict__ partial) {
-  // blockIdx.y selects the plane (wave-uniform stencil, scalar loads)
+  // blockIdx.y selects the plane; its stencil is staged in LDS.  The three
+  // neighbour planes are visited in a loop that is not unrolled: each visit
+  // issues its 27 loads together, so a thread waits for three rounds of memory
+  // latency and holds one plane's neighbours in registers.
+  __shared__ T sc[243];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 1 + static_cast<int>(blockIdx.y);
-  double sq = 0.0;
-  if (t < nx * ny) {
-    const int P = nx * ny, C = (nz + 1) * P;
-    const int i = t % nx, j = t / nx;
-    const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
-    const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-    const T* Sk = S + static_cast<size_t>(__builtin_amdgcn_readfirstlane(k)) * 243;
-    const int o = k * P + j * nx + i;
-    T acc[3];
+  const bool active = t < nx * ny;
+  for (int e = threadIdx.x; e < 243; e += blockDim.x) sc[e] = S[static_cast<size_t>(k) * 243 + e];
+  const int tt = active ? t : 0;
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int i = tt % nx, j = tt / nx;
+  const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
+  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
+  const int o = k * P + j * nx + i;
+  T acc[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
+  for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
+  __syncthreads();
+#pragma unroll 1
+  for (int oz = 0; oz < 3; ++oz) {
+    const int kk = k + oz - 1;
+    if (ZERO_INT && kk != 0 && kk != nz) continue;
+    T nb[9][3];
 #pragma unroll
-    for (int oz = 0; oz < 3; ++oz) {
-      const int kk = k + oz - 1;
-      if (ZERO_INT && kk != 0 && kk != nz) continue;
+    for (int q = 0; q < 9; ++q) {
+      const int off = kk * P + ys[q / 3] * nx + xs[q % 3];
 #pragma unroll
-      for (int oy = 0; oy < 3; ++oy)
-#pragma unroll
-        for (int ox = 0; ox < 3; ++ox) {
-          const int q = oz * 9 + oy * 3 + ox;
-          const int off = kk * P + ys[oy] * nx + xs[ox];
-          const T n0 = x[off], n1 = x[C + off], n2 = x[2 * C + off];
-          const T* B = Sk + q * 9;
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            acc[c] -= B[c * 3] * n0 + B[c * 3 + 1] * n1 + B[c * 3 + 2] * n2;
-        }
+      for (int c = 0; c < 3; ++c) nb[q][c] = x[c * C + off];
     }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const T* B = sc + (oz * 9 + q) * 9;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        acc[c] -= B[c * 3] * nb[q][0] + B[c * 3 + 1] * nb[q][1] + B[c * 3 + 2] * nb[q][2];
+    }
+  }
+  double sq = 0.0;
+  if (active) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       sq += static_cast<double>(acc[c]) * static_cast<double>(acc[c]);
