@@ -85,6 +85,31 @@ def test_colour_passes(n, level):
         assert rel(host(xd), x) < 1e-13, c
 
 
+def test_colour_passes_wide_coarse_level():
+    """A coarse level wider than a wavefront's colour row (80 x 12 x 8): colour
+    passes match the oracle colour by colour, and whole V-cycles on this
+    hierarchy match the oracle's iterates."""
+    rng = np.random.default_rng(11)
+    n = (160, 24, 16)
+    g, o = make(*n, min_coarse_nz=4)
+    L = o.levels[1]
+    assert (L.nx, L.ny, L.nz) == (80, 12, 8)
+    x = rand_node(rng, L.nx, L.ny, L.nz, walls=False)
+    b = rand_node(rng, L.nx, L.ny, L.nz)
+    xd, bd = dev(x), dev(b)
+    for c in [3, 0, 6, 5, 1, 7, 2, 4]:
+        g.level_colour_pass(1, xd, bd, c)
+        L.colour_pass(x, b, (c & 1, (c >> 1) & 1, (c >> 2) & 1))
+        assert rel(host(xd), x) < 1e-13, c
+    bf = rand_node(rng, *n)
+    x0 = rand_node(rng, *n)
+    for k in (1, 3):
+        xd = dev(x0)
+        g.solve(dev(bf), xd, rtol=0.0, max_cycles=k)
+        x_ref, _ = o.solve(bf, x0, rtol=0.0, max_cycles=k)
+        assert rel(host(xd), x_ref) < 1e-12, k
+
+
 @pytest.mark.parametrize("n", GRIDS)
 def test_residual_restrict_prolong(n):
     rng = np.random.default_rng(3)
