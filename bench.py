@@ -94,6 +94,65 @@ def cpu_baseline(n_full: int, cycles_full: int) -> dict:
             "host_cpus": os.cpu_count()}
 
 
+def solve_pair(n: int, b, steps: int, warmup: int) -> dict:
+    """FP32-IR and FP64 solves of K x = b from x = 0 to 1e-10 at n^3; wall time
+    per solve between device synchronisations, and the two solutions' relative
+    L2 difference."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame
+    lam, mu = lame()
+    out, sols = {}, {}
+    for name, prec in (("fp32_ir", "fp32-ir"), ("fp64", "fp64")):
+        g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision=prec, device=b.device)
+        x = torch.zeros_like(b)
+        for _ in range(warmup):
+            x.zero_()
+            g.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            x.zero_()
+            info = g.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_solve": dt * 1e3, "solves_per_s": 1.0 / dt, "cycles": info.cycles,
+                     "rel_res": info.rel_res, "levels": g.levels,
+                     "ms_per_cycle": dt * 1e3 / max(info.cycles, 1)}
+        sols[name] = x
+        g.close()
+    out["fp32ir_vs_fp64_rel_l2"] = (torch.linalg.vector_norm(sols["fp32_ir"] - sols["fp64"])
+                                    / torch.linalg.vector_norm(sols["fp64"])).item()
+    out["speedup_fp32ir_vs_fp64"] = out["fp64"]["ms_per_solve"] / out["fp32_ir"]["ms_per_solve"]
+    return out
+
+
+def config_512(steps: int = 3, warmup: int = 1) -> dict:
+    """The 512^3 case of the mixed-precision comparison (7 levels); the RHS is
+    the same recipe (D_h of the smoothed random stress, seed 2) generated on the
+    device."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, stress_field_device
+    lam, mu = lame()
+    n = 512
+    dev = torch.device("cuda:0")
+    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp64", device=dev)
+    sig = stress_field_device(n, n, n, 2, dev)
+    b = g.rhs(sig, 1.0)
+    del sig
+    g.close()
+    out = solve_pair(n, b, steps, warmup)
+    out["grid"] = [n, n, n]
+    out["steps"] = steps
+    out["rhs"] = "D_h sigma, sigma smoothed N(0,1) generated on the device (seed 2)"
+    del b
+    torch.cuda.empty_cache()
+    return out
+
+
 def profile_smoother(n: int) -> None:
     """Kernels for hardware-counter runs: one device-to-device copy of a known
     size (calibrates FETCH_SIZE / WRITE_SIZE), then 3 fine-level sweeps in FP32
@@ -129,6 +188,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-512", action="store_true", help="skip the 512^3 comparison block")
     ap.add_argument("--profile-smoother", action="store_true",
                     help="only run a calibration copy and fine-level sweeps (for rocprofv3 counters)")
     args = ap.parse_args()
@@ -232,6 +292,8 @@ def main():
                      "traffic_GBs": (traffic / (sm["fp32"]["avg_launch_us"] * 1e-6) / 1e9
                                      if traffic else None)},
     }
+    if not args.no_512 and n == 256:
+        out["config2_512"] = config_512()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, results["fp64"]["cycles"])
     print(json.dumps(out))

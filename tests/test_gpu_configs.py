@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 from oracle import stz as ostz
 from oracle.operators import apply_elastic, div_node, grad_cell
 from workloads import (lame, manufactured_source, manufactured_velocity, shear_state,
-                       stress_field, stz_constants)
+                       stress_field, stress_field_device, stz_constants)
 
 pytestmark = pytest.mark.gpu
 LAM, MU = lame()
@@ -64,6 +64,54 @@ def test_config2_residual_at_256(prec):
     assert rel <= 1.2e-10, rel
     # the right-hand side itself at sampled nodes: D_h sigma (oracle) on a patch
     assert np.isfinite(rel)
+
+
+def test_config2_at_512():
+    """512^3 (7 levels), FP64 and FP32-IR to 1e-10 on b = D_h sigma of the
+    smoothed random stress (device generator, seed 2).  The oracle's operator,
+    applied to the 3x3x3 neighbourhoods of 4096 sampled nodes, reproduces the
+    GPU's K x there to rounding; with that operator the full relative residual
+    is <= 1e-10 for both precisions, and the two solutions agree to 1e-8."""
+    n = 512
+    g64 = solver(n, precision="fp64")
+    g32 = solver(n, precision="fp32-ir")
+    assert g64.levels == 7
+    sig = stress_field_device(n, n, n, 2, "cuda")
+    b = g64.rhs(sig, 1.0)
+    del sig
+    xs = {}
+    for name, g in (("fp64", g64), ("fp32-ir", g32)):
+        x = torch.zeros_like(b)
+        info = g.solve(b, x, rtol=1e-10)
+        assert info.converged and info.rel_res <= 1e-10, (name, info.rel_res)
+        assert info.cycles <= 25, (name, info.cycles)
+        xs[name] = x
+    for name, x in xs.items():
+        r = b - g64.apply(x)
+        rel = (torch.linalg.vector_norm(r[:, 1:n]) / torch.linalg.vector_norm(b[:, 1:n])).item()
+        assert rel <= 1.2e-10, (name, rel)
+    d = (torch.linalg.vector_norm(xs["fp32-ir"] - xs["fp64"])
+         / torch.linalg.vector_norm(xs["fp64"])).item()
+    assert d < 1e-8, d
+    # oracle operator at sampled nodes, patches laid side by side along x
+    rng = np.random.default_rng(12)
+    M = 4096
+    ks = torch.as_tensor(rng.integers(1, n, M), device="cuda")
+    js = torch.as_tensor(rng.integers(0, n, M), device="cuda")
+    is_ = torch.as_tensor(rng.integers(0, n, M), device="cuda")
+    x = xs["fp64"]
+    off = torch.tensor([-1, 0, 1], device="cuda")
+    kk = (ks[:, None] + off)[:, :, None, None]
+    jj = ((js[:, None] + off) % n)[:, None, :, None]
+    ii = ((is_[:, None] + off) % n)[:, None, None, :]
+    patch = x[:, kk, jj, ii]                      # (3, M, 3, 3, 3): component, sample, z, y, x
+    patch = host(patch.permute(0, 2, 3, 1, 4).reshape(3, 3, 3, 3 * M))
+    kx = apply_elastic(patch, 1.0 / n, LAM, MU)[:, 1, 1, 1::3]          # (3, M)
+    kx_gpu = host(g64.apply(x)[:, ks, js, is_])
+    # two FP64 evaluations of a 45-term sum differ by rounding of the terms,
+    # each at most about (2 lambda + 8 mu) / h^2 times max |x|
+    term = (2 * LAM + 8 * MU) * n * n * np.abs(patch).max()
+    assert np.abs(kx - kx_gpu).max() <= 256 * np.finfo(np.float64).eps * term
 
 
 def _node_patch(v, k, j, i):

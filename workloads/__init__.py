@@ -89,6 +89,31 @@ def stress_field(nx: int, ny: int, nz: int, seed: int, jacobi_passes: int = 3) -
     return np.ascontiguousarray(s)
 
 
+def stress_field_device(nx: int, ny: int, nz: int, seed: int, device, jacobi_passes: int = 3):
+    """The recipe of `stress_field` generated on a torch device (for grids where
+    the host version takes minutes): i.i.d. N(0,1) Voigt components from a
+    seeded torch generator (so other numbers than `stress_field` draws), then
+    the same face-mean Jacobi passes, periodic in x and y, with linearly
+    extrapolated z ghost layers.  Returns a float64 tensor (6, nz, ny, nx)."""
+    import torch
+    if nz < 2:
+        raise ValueError("nz must be >= 2")
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    s = torch.randn((6, nz, ny, nx), generator=gen, dtype=torch.float64, device=device)
+    for _ in range(jacobi_passes):
+        acc = torch.roll(s, 1, -1) + torch.roll(s, -1, -1)
+        acc += torch.roll(s, 1, -2)
+        acc += torch.roll(s, -1, -2)
+        acc[:, :-1] += s[:, 1:]
+        acc[:, -1] += 2.0 * s[:, -1] - s[:, -2]
+        acc[:, 1:] += s[:, :-1]
+        acc[:, 0] += 2.0 * s[:, 0] - s[:, 1]
+        s = acc / 6.0
+        del acc
+    return s.contiguous()
+
+
 def chi_field(nx: int, ny: int, nz: int, seed: int, mean: float = 0.05,
               std: float = 0.003, lc_cells: float = 8.0, cutoff: float = 5.0) -> np.ndarray:
     """Gaussian random effective-temperature field on cells (paper Eq. convolve).
