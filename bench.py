@@ -246,10 +246,13 @@ def main():
         xs = torch.zeros(g.node_shape(0), dtype=dt_, device=dev)
         bs = b.to(dt_)
         g.smooth(0, xs, bs, 1)
-        sweeps = 4
-        ms = _events_ms(lambda: g.smooth(0, xs, bs, sweeps), 3) / sweeps
-        # one sweep = two row-parity half sweeps (kernel k_sweep_rows), each
-        # updating half of the nodes
+        # one call also moves the wall planes of the ping-pong buffer; the
+        # difference of a 5-sweep and a 1-sweep call leaves 4 sweeps of the
+        # kernel alone.  One sweep = two row-parity half sweeps (k_sweep_rows),
+        # each updating half of the nodes.
+        t5 = _events_ms(lambda: g.smooth(0, xs, bs, 5), 5)
+        t1 = _events_ms(lambda: g.smooth(0, xs, bs, 1), 5)
+        ms = (t5 - t1) / 4
         sm[name] = {"ms_per_sweep": ms, "launches_per_sweep": 2,
                     "avg_launch_us": ms * 1e3 / 2,
                     "effective_GBs": bpn * nodes / (ms * 1e-3) / 1e9}

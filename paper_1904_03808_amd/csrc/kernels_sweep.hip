@@ -76,27 +76,35 @@ struct SweepArgs {
 
 constexpr int kPad = 2;  // LDS row: [unused][copy of col nx-1][cols 0..nx-1][copy of col 0][unused]
 
-int rows_per_group(int nx) { return std::max(1, 256 / nx); }
+// rows of one parity per workgroup: two at 256 columns, more for shorter rows
+// (at most 256 threads), one at 512
+int rows_per_group(int nx) { return std::max(1, std::min(64, 512 / nx)); }
 
 // Per-thread state of the sweep, passed by value so that it stays in registers.
 template <typename T, int NX>
 struct Ctx {
-  T* ring;   // [4 planes][rows][9 = row (j-1, j, j+1) x component][NXP]
+  T* ring;   // [4 planes][2 rows + 1][3 components][NXP]: rows j0-1 .. j0+2 rows-1
   int nx;    // row length (NX when NX > 0)
   int rows;  // rows per workgroup
-  int r;     // row of this thread within the workgroup
+  int r;     // row of this thread within the workgroup (ring rows 2r .. 2r+2)
   int c0;    // first column of this thread's pair
   int tpr;   // threads per row
   int j, jm, jp;
   size_t P, C;
-  bool write;  // false for the copies of a valid row that pad the last group
+  bool write;  // false for rows past the last one of this parity (last group)
   __device__ __forceinline__ int nxp() const { return (NX > 0 ? NX : nx) + 2 * kPad; }
-  // column 0 of LDS row q of the plane held in ring slot (plane & 3)
+  // column 0 of LDS row q = 3 rr + component of this thread's rows
+  // (rr 0, 1, 2 = j-1, j, j+1) in the plane held in ring slot (plane & 3);
+  // the rows of a workgroup are consecutive, so the neighbour row between two
+  // of its rows is stored once
   __device__ __forceinline__ T* row(int plane, int q) const {
-    return ring + (((plane & 3) * rows + r) * 9 + q) * nxp() + kPad;
+    return ring + (((plane & 3) * (2 * rows + 1) + 2 * r) * 3 + q) * nxp() + kPad;
   }
 };
 
+// Values of one plane that a thread moves into the ring: its rows j-1 and j,
+// and the row j+1 for the workgroup's last row (the other rows j+1 are the
+// next thread row's j-1).
 template <typename T>
 struct PlaneRegs {
   typename V2<T>::type v[9];
@@ -112,11 +120,15 @@ __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __rest
   const size_t om = o + static_cast<size_t>(c.jm) * nx;
   const size_t oo = o + static_cast<size_t>(c.j) * nx;
   const size_t op = o + static_cast<size_t>(c.jp) * nx;
+  const bool top = c.r == c.rows - 1;  // uniform over a wavefront's row
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     out.v[k] = *reinterpret_cast<const V*>(nbr_src + k * c.C + om);
     out.v[3 + k] = *reinterpret_cast<const V*>(own_src + k * c.C + oo);
-    out.v[6 + k] = *reinterpret_cast<const V*>(nbr_src + k * c.C + op);
+  }
+  if (top) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) out.v[6 + k] = *reinterpret_cast<const V*>(nbr_src + k * c.C + op);
   }
 }
 
@@ -130,11 +142,14 @@ __device__ __forceinline__ void store_plane(const Ctx<T, NX>& c, int p, const Pl
   const bool hi = c.c0 == nx - 2;
   const int g = c.c0 == 0 ? nx : (hi ? -1 : c.c0);
   T* base = c.row(p, 0);
+  const int nq = c.r == c.rows - 1 ? 9 : 6;
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    T* rw = base + q * c.nxp();
-    *reinterpret_cast<V*>(rw + c.c0) = in.v[q];
-    rw[g] = hi ? in.v[q].y : in.v[q].x;
+    if (q < nq) {
+      T* rw = base + q * c.nxp();
+      *reinterpret_cast<V*>(rw + c.c0) = in.v[q];
+      rw[g] = hi ? in.v[q].y : in.v[q].x;
+    }
   }
 }
 
@@ -304,11 +319,12 @@ __global__ __launch_bounds__(256) void k_sweep_rows(const T* __restrict__ own_sr
   c.r = threadIdx.x / c.tpr;
   c.c0 = 2 * (threadIdx.x - c.r * c.tpr);
   // threads = rows * tpr, so every thread has a row slot; rows past the last
-  // row of this parity (last group only) repeat that row without writing it
+  // row of this parity (last group only) are computed on the wrapped row
+  // index, which keeps the shared neighbour rows consistent, and not written
   const int jr = 2 * (group * a.rows + c.r) + a.row_par;
   const int jlast = a.ny - 2 + a.row_par;
   c.write = jr <= jlast;
-  c.j = c.write ? jr : jlast;
+  c.j = jr % a.ny;
   c.jm = c.j == 0 ? a.ny - 1 : c.j - 1;
   c.jp = c.j + 1 >= a.ny ? c.j + 1 - a.ny : c.j + 1;
   c.P = static_cast<size_t>(c.nx) * a.ny;
@@ -429,7 +445,7 @@ int sweep_segment_length(Dims d, int bytes_per_value) {
 }
 
 int sweep_lds_bytes(Dims d, int bytes_per_value) {
-  return 4 * rows_per_group(d.nx) * 9 * (d.nx + 2 * kPad) * bytes_per_value;
+  return 4 * (2 * rows_per_group(d.nx) + 1) * 3 * (d.nx + 2 * kPad) * bytes_per_value;
 }
 
 bool sweep_supported(Dims d, size_t lds_limit, int bytes_per_value) {
