@@ -267,8 +267,12 @@ bool use_row_sweep(qs_handle* hd, int l) {
 // `sweeps` Gauss-Seidel sweeps on level l, in the colour order given at
 // setup (forward) or its reverse.  The row-parity kernel ping-pongs between
 // x and the level's second buffer; an odd sweep count ends with a copy back.
+// x_zero: the interior of x is known to be zero (its walls are zero too), so
+// the first forward sweep does not read it; the sweep writes every interior
+// node of the other buffer, so x need not even hold zeros then.
 template <typename T>
-void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse) {
+void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse,
+            bool x_zero = false) {
   if (sweeps <= 0) return;
   LevelBufs& lb = hd->L[l];
   const int* ord = hd->p.colour_order;
@@ -285,9 +289,11 @@ void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse) {
   T* oth = y;
   const int rp0 = reverse ? 1 : 0, pf = reverse ? 1 : 0, xf = reverse ? 1 : 0;
   for (int s = 0; s < sweeps; ++s) {
-    launch_sweep_half<T>(cur, cur, oth, b, lb.d, rp0, pf, xf, cf, Prec<T>::seg(lb), 1, hd->stream);
-    launch_sweep_half<T>(cur, oth, oth, b, lb.d, 1 - rp0, pf, xf, cf, Prec<T>::seg(lb), 1,
+    const bool z = x_zero && s == 0 && !reverse;
+    launch_sweep_half<T>(cur, cur, oth, b, lb.d, rp0, pf, xf, cf, Prec<T>::seg(lb), 1, z ? 2 : 0,
                          hd->stream);
+    launch_sweep_half<T>(cur, oth, oth, b, lb.d, 1 - rp0, pf, xf, cf, Prec<T>::seg(lb), 1,
+                         z ? 1 : 0, hd->stream);
     T* t = cur;
     cur = oth;
     oth = t;
@@ -296,14 +302,16 @@ void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse) {
     (void)hipMemcpyAsync(x, cur, lb.d.elems() * sizeof(T), hipMemcpyDeviceToDevice, hd->stream);
 }
 
+// x_zero: x is zero on entry and need not hold it (see smooth; only when the
+// row sweep smooths level l and n_pre >= 1)
 template <typename T>
-void vcycle(qs_handle* hd, int l, T* x, const T* b) {
+void vcycle(qs_handle* hd, int l, T* x, const T* b, bool x_zero = false) {
   LevelBufs& lb = hd->L[l];
   if (l == hd->nlev - 1) {
     coarse_solve<T>(hd, l, x, b, Prec<T>::r(lb));
     return;
   }
-  smooth<T>(hd, l, x, b, hd->p.n_pre, false);
+  smooth<T>(hd, l, x, b, hd->p.n_pre, false, x_zero);
   LevelBufs& cb = hd->L[l + 1];
   if (l == 0) {
     launch_resid_restrict<T>(x, b, Prec<T>::b(cb), lb.d, hd->fc64, hd->stream);
@@ -436,6 +444,9 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
     }
     if (lb.y64) launch_fill<double>(lb.y64, lb.d.elems(), 0.0, hd->stream);
     if (lb.y32) launch_fill<float>(lb.y32, lb.d.elems(), 0.0f, hd->stream);
+    // the FP32 correction of the fine level: walls stay zero for good (the
+    // refinement loop may skip clearing its interior, see solve_impl)
+    if (l == 0 && lb.x32) launch_fill<float>(lb.x32, lb.d.elems(), 0.0f, hd->stream);
   }
   // upload stencils (FP64 and their FP32 roundings) and the coarse inverse;
   // the staging vectors live until the synchronisation below
@@ -554,8 +565,9 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
     if (ir) {
       // correction e solves A e = r / scale_used in FP32; x += scale_used e
       LevelBufs& l0 = hd->L[0];
-      launch_fill<float>(l0.x32, l0.d.elems(), 0.0f, hd->stream);
-      vcycle<float>(hd, 0, l0.x32, l0.b32);
+      const bool skip_fill = hd->p.n_pre >= 1 && hd->nlev > 1 && use_row_sweep<float>(hd, 0);
+      if (!skip_fill) launch_fill<float>(l0.x32, l0.d.elems(), 0.0f, hd->stream);
+      vcycle<float>(hd, 0, l0.x32, l0.b32, skip_fill);
       launch_ir_update(x, l0.x32, d0, scale_used, hd->stream);
     } else {
       vcycle<double>(hd, 0, x, b);

@@ -36,11 +36,12 @@ void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T
 
 // Fine-level row-parity half sweep (kernels_sweep.hip): updates every node
 // of the rows with parity row_par, reading own rows from own_src, neighbour
-// rows from nbr_src and writing dst.
+// rows from nbr_src and writing dst.  zero = 1: own rows are known to be 0
+// and not read; zero = 2: own and neighbour rows (x_first = 0 only).
 template <typename T>
 void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
                        int plane_first, int x_first, const FineCoef<T>& cf, int seg, int seg_major,
-                       hipStream_t s);
+                       int zero, hipStream_t s);
 int sweep_rows_per_group(int nx);  // rows of one parity per workgroup
 int sweep_segment_length(Dims d, int bytes_per_value);  // z planes per workgroup
 int sweep_lds_bytes(Dims d, int bytes_per_value);

@@ -110,7 +110,10 @@ struct PlaneRegs {
   typename V2<T>::type v[9];
 };
 
-template <typename T, int NX>
+// Z = 0: rows as stored; Z = 1: the thread's own row reads as zero; Z = 2:
+// own and neighbour rows read as zero (a vector known to be zero is not
+// fetched).
+template <typename T, int NX, int Z>
 __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __restrict__ own_src,
                                             const T* __restrict__ nbr_src, int p,
                                             PlaneRegs<T>& out) {
@@ -121,14 +124,16 @@ __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __rest
   const size_t oo = o + static_cast<size_t>(c.j) * nx;
   const size_t op = o + static_cast<size_t>(c.jp) * nx;
   const bool top = c.r == c.rows - 1;  // uniform over a wavefront's row
+  const V zero = V{T(0), T(0)};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    out.v[k] = *reinterpret_cast<const V*>(nbr_src + k * c.C + om);
-    out.v[3 + k] = *reinterpret_cast<const V*>(own_src + k * c.C + oo);
+    out.v[k] = Z >= 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + om);
+    out.v[3 + k] = Z >= 1 ? zero : *reinterpret_cast<const V*>(own_src + k * c.C + oo);
   }
   if (top) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) out.v[6 + k] = *reinterpret_cast<const V*>(nbr_src + k * c.C + op);
+    for (int k = 0; k < 3; ++k)
+      out.v[6 + k] = Z >= 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + op);
   }
 }
 
@@ -254,27 +259,27 @@ struct StepRegs {
 };
 
 // Issue the loads of the step whose planes are g = f+2 and g+1.
-template <typename T, int NX>
+template <typename T, int NX, int Z>
 __device__ __forceinline__ void fetch_step(const Ctx<T, NX>& c, const T* __restrict__ own_src,
                                            const T* __restrict__ nbr_src, const T* __restrict__ b,
                                            int g, int nz, StepRegs<T>& s) {
   fetch_b<T, NX>(c, b, g, nz, s.bf);
   fetch_b<T, NX>(c, b, g - 1, nz, s.bs);
-  fetch_plane<T, NX>(c, own_src, nbr_src, min(g, nz), s.p2);
-  fetch_plane<T, NX>(c, own_src, nbr_src, min(g + 1, nz), s.p3);
+  fetch_plane<T, NX, Z>(c, own_src, nbr_src, min(g, nz), s.p2);
+  fetch_plane<T, NX, Z>(c, own_src, nbr_src, min(g + 1, nz), s.p3);
 }
 
 // One step of the march: issue the loads for two steps ahead into `nxt`,
 // update planes f and f-1 from the ring, then move `cur` (planes f+2, f+3)
 // into the slots of f-2 and f-1 and its b values into bf / bs.
-template <typename T, int NX, int X1>
+template <typename T, int NX, int X1, int Z>
 __device__ __forceinline__ void march_step(const Ctx<T, NX>& c, const T* __restrict__ own_src,
                                            const T* __restrict__ nbr_src, const T* __restrict__ b,
                                            T* __restrict__ dst, const FineCoef<T>& cf, int f,
                                            int z0, int z1, int nz, typename V2<T>::type bf[3],
                                            typename V2<T>::type bs[3], StepRegs<T>& cur,
                                            StepRegs<T>& nxt) {
-  fetch_step<T, NX>(c, own_src, nbr_src, b, f + 4, nz, nxt);
+  fetch_step<T, NX, Z>(c, own_src, nbr_src, b, f + 4, nz, nxt);
   update_plane<T, NX, X1>(c, f, z0, z1, bf, cf, dst);
   __syncthreads();
   const int sp = f - 1;  // second-parity plane below f
@@ -292,7 +297,7 @@ __device__ __forceinline__ void march_step(const Ctx<T, NX>& c, const T* __restr
   __syncthreads();
 }
 
-template <typename T, int NX, int X1>
+template <typename T, int NX, int X1, int Z>
 __global__ __launch_bounds__(256) void k_sweep_rows(const T* __restrict__ own_src,
                                                     const T* __restrict__ nbr_src,
                                                     T* __restrict__ dst, const T* __restrict__ b,
@@ -357,11 +362,11 @@ __global__ __launch_bounds__(256) void k_sweep_rows(const T* __restrict__ own_sr
   StepRegs<T> ra, rb;
   {
     PlaneRegs<T> q0, q1, q2, q3;
-    fetch_plane<T, NX>(c, own_src, nbr_src, max(f0 - 2, 0), q0);
-    fetch_plane<T, NX>(c, own_src, nbr_src, f0 - 1, q1);
-    fetch_plane<T, NX>(c, own_src, nbr_src, f0, q2);
-    fetch_plane<T, NX>(c, own_src, nbr_src, f0 + 1, q3);  // f0 + 1 <= nz
-    fetch_step<T, NX>(c, own_src, nbr_src, b, f0 + 2, nz, ra);
+    fetch_plane<T, NX, Z>(c, own_src, nbr_src, max(f0 - 2, 0), q0);
+    fetch_plane<T, NX, Z>(c, own_src, nbr_src, f0 - 1, q1);
+    fetch_plane<T, NX, Z>(c, own_src, nbr_src, f0, q2);
+    fetch_plane<T, NX, Z>(c, own_src, nbr_src, f0 + 1, q3);  // f0 + 1 <= nz
+    fetch_step<T, NX, Z>(c, own_src, nbr_src, b, f0 + 2, nz, ra);
     if (first == f0 - 2) store_plane<T, NX>(c, f0 - 2, q0);
     store_plane<T, NX>(c, f0 - 1, q1);
     store_plane<T, NX>(c, f0, q2);
@@ -369,9 +374,9 @@ __global__ __launch_bounds__(256) void k_sweep_rows(const T* __restrict__ own_sr
   }
   __syncthreads();
   for (int f = f0;; f += 4) {
-    march_step<T, NX, X1>(c, own_src, nbr_src, b, dst, cf, f, z0, z1, nz, bf, bs, ra, rb);
+    march_step<T, NX, X1, Z>(c, own_src, nbr_src, b, dst, cf, f, z0, z1, nz, bf, bs, ra, rb);
     if (f + 2 > flast) break;
-    march_step<T, NX, X1>(c, own_src, nbr_src, b, dst, cf, f + 2, z0, z1, nz, bf, bs, rb, ra);
+    march_step<T, NX, X1, Z>(c, own_src, nbr_src, b, dst, cf, f + 2, z0, z1, nz, bf, bs, rb, ra);
     if (f + 4 > flast) break;
   }
   const int sp = flast + 1;  // only when flast + 2 is the top wall (already in the ring)
@@ -380,31 +385,38 @@ __global__ __launch_bounds__(256) void k_sweep_rows(const T* __restrict__ own_sr
 
 template <typename T, int NX>
 void launch_nx(const T* own_src, const T* nbr_src, T* dst, const T* b, const SweepArgs& a,
-               const FineCoef<T>& cf, int threads, size_t lds, hipStream_t s) {
+               const FineCoef<T>& cf, int zero, int threads, size_t lds, hipStream_t s) {
+  const dim3 grid(8 * a.grid_per_xcd), block(threads);
   if (a.x_first)
-    hipLaunchKernelGGL((k_sweep_rows<T, NX, 1>), dim3(8 * a.grid_per_xcd), dim3(threads), lds, s,
-                       own_src, nbr_src, dst, b, a, cf);
+    hipLaunchKernelGGL((k_sweep_rows<T, NX, 1, 0>), grid, block, lds, s, own_src, nbr_src, dst, b,
+                       a, cf);
+  else if (zero == 2)
+    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0, 2>), grid, block, lds, s, own_src, nbr_src, dst, b,
+                       a, cf);
+  else if (zero == 1)
+    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0, 1>), grid, block, lds, s, own_src, nbr_src, dst, b,
+                       a, cf);
   else
-    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0>), dim3(8 * a.grid_per_xcd), dim3(threads), lds, s,
-                       own_src, nbr_src, dst, b, a, cf);
+    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0, 0>), grid, block, lds, s, own_src, nbr_src, dst, b,
+                       a, cf);
 }
 
-template <typename T, int NX, int X1>
+template <typename T, int NX>
 void set_lds_limit_one(int bytes) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep_rows<T, NX, X1>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* k[4] = {reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 0>),
+                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 1, 0>),
+                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 1>),
+                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 2>)};
+  for (const void* f : k)
+    (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <typename T>
 void set_lds_limit_all(int bytes) {
-  set_lds_limit_one<T, 0, 0>(bytes);
-  set_lds_limit_one<T, 0, 1>(bytes);
-  set_lds_limit_one<T, 128, 0>(bytes);
-  set_lds_limit_one<T, 128, 1>(bytes);
-  set_lds_limit_one<T, 256, 0>(bytes);
-  set_lds_limit_one<T, 256, 1>(bytes);
-  set_lds_limit_one<T, 512, 0>(bytes);
-  set_lds_limit_one<T, 512, 1>(bytes);
+  set_lds_limit_one<T, 0>(bytes);
+  set_lds_limit_one<T, 128>(bytes);
+  set_lds_limit_one<T, 256>(bytes);
+  set_lds_limit_one<T, 512>(bytes);
 }
 
 }  // namespace
@@ -416,10 +428,10 @@ int blocks_per_cu(Dims d, int threads, size_t lds) {
   int n = 0;
   const void* k = nullptr;
   switch (d.nx) {
-    case 128: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 128, 0>); break;
-    case 256: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 256, 0>); break;
-    case 512: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 512, 0>); break;
-    default: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 0, 0>); break;
+    case 128: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 128, 0, 0>); break;
+    case 256: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 256, 0, 0>); break;
+    case 512: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 512, 0, 0>); break;
+    default: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 0, 0, 0>); break;
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) n = 1;
   return std::max(n, 1);
@@ -456,7 +468,7 @@ bool sweep_supported(Dims d, size_t lds_limit, int bytes_per_value) {
 template <typename T>
 void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
                        int plane_first, int x_first, const FineCoef<T>& cf, int seg,
-                       int seg_major, hipStream_t s) {
+                       int seg_major, int zero, hipStream_t s) {
   SweepArgs a;
   a.nx = d.nx;
   a.ny = d.ny;
@@ -475,10 +487,10 @@ void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, D
   const int threads = a.rows * (d.nx / 2);
   const size_t lds = static_cast<size_t>(sweep_lds_bytes(d, sizeof(T)));
   switch (d.nx) {
-    case 128: launch_nx<T, 128>(own_src, nbr_src, dst, b, a, cf, threads, lds, s); break;
-    case 256: launch_nx<T, 256>(own_src, nbr_src, dst, b, a, cf, threads, lds, s); break;
-    case 512: launch_nx<T, 512>(own_src, nbr_src, dst, b, a, cf, threads, lds, s); break;
-    default: launch_nx<T, 0>(own_src, nbr_src, dst, b, a, cf, threads, lds, s); break;
+    case 128: launch_nx<T, 128>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
+    case 256: launch_nx<T, 256>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
+    case 512: launch_nx<T, 512>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
+    default: launch_nx<T, 0>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
   }
 }
 
@@ -488,9 +500,10 @@ void sweep_set_lds_limit(size_t bytes) {
 }
 
 template void launch_sweep_half<double>(const double*, const double*, double*, const double*, Dims,
-                                        int, int, int, const FineCoef<double>&, int, int,
+                                        int, int, int, const FineCoef<double>&, int, int, int,
                                         hipStream_t);
 template void launch_sweep_half<float>(const float*, const float*, float*, const float*, Dims, int,
-                                       int, int, const FineCoef<float>&, int, int, hipStream_t);
+                                       int, int, const FineCoef<float>&, int, int, int,
+                                       hipStream_t);
 
 }  // namespace qs
