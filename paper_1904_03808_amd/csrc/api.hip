@@ -29,6 +29,7 @@ struct LevelBufs {
   float* b32 = nullptr;
   float* r32 = nullptr;
   double* y64 = nullptr;  // second smoother buffer (ping-pong), smoothed levels
+  double* xalt64 = nullptr;  // FP32-IR, fine level: the other buffer of the FP64 iterate
   float* y32 = nullptr;
   int seg64 = 16, seg32 = 16;  // z planes per workgroup of the row sweep (fine level)
   double* S64 = nullptr;
@@ -113,6 +114,7 @@ void carve(const qs_params* p, const std::vector<int>& dims, char* base, qs_hand
       lb.r64 = cv.take<double>(e);
       if (l < nlev - 1) lb.y64 = cv.take<double>(e);
     } else {
+      if (l == 0) lb.xalt64 = cv.take<double>(e);
       lb.x32 = cv.take<float>(e);
       lb.b32 = cv.take<float>(e);
       if (l < nlev - 1) {
@@ -531,6 +533,20 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   const bool fixed = !(rtol > 0.0);
   const bool ir = hd->p.precision == QS_FP32_IR;
   if (!ir && hd->L[0].y64) copy_walls<double>(x, hd->L[0].y64, d0, hd->stream);
+  // FP32-IR: the update x += s e of one cycle is made by the next residual
+  // kernel, out of place, so the iterate alternates between x and xalt64
+  // (whose wall planes take the Dirichlet data once per solve)
+  LevelBufs& l0 = hd->L[0];
+  double* xs = x;
+  if (ir) copy_walls<double>(x, l0.xalt64, d0, hd->stream);
+  bool pending = false;  // a correction in l0.x32 not yet added to xs
+  double e_scale = 0.0;
+  auto finish = [&](qs_status st) {
+    if (xs != x)
+      (void)hipMemcpyAsync(x, xs, d0.elems() * sizeof(double), hipMemcpyDeviceToDevice,
+                           hd->stream);
+    return st;
+  };
   double scale = pow2_near(std::sqrt(nb2 / nunk));
   double scale_used = scale;
   int cycles = 0;
@@ -540,42 +556,52 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
     if (ir) {
       // FP64 residual, written as FP32 scaled by 1/scale for the inner cycle
       scale_used = scale;
-      residual_norm0<float>(hd, x, b, hd->L[0].b32, 1.0 / scale_used, false);
+      if (pending) {
+        double* xn = xs == x ? l0.xalt64 : x;
+        const int nb = launch_update_residual_zm(xs, l0.x32, e_scale, xn, b, l0.b32, d0, hd->fc64,
+                                                 1.0 / scale_used, hd->partial, hd->stream);
+        launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->stream);
+        xs = xn;
+        pending = false;
+      } else {
+        residual_norm0<float>(hd, xs, b, l0.b32, 1.0 / scale_used, false);
+      }
     } else if (need_norm) {
       residual_norm0<double>(hd, x, b, nullptr, 1.0, false);
     }
     if (need_norm) {
       double rn2 = 0.0;
       st = read_norm(hd, &rn2);
-      if (st != QS_OK) return st;
+      if (st != QS_OK) return finish(st);
       rel = std::sqrt(rn2 / nb2);
       if (cycles < QS_HIST) inf->rel_res_hist[cycles] = rel;
       inf->rel_res = rel;
       if (!std::isfinite(rel)) {
         inf->cycles = cycles;
-        return QS_ERR_NONFINITE;
+        return finish(QS_ERR_NONFINITE);
       }
       if (!fixed && rel <= rtol) break;
       if (ir) scale = pow2_near(std::sqrt(rn2 / nunk));
     }
     if (cycles == max_cycles) {
       inf->cycles = cycles;
-      return fixed ? QS_OK : QS_ERR_NOT_CONVERGED;
+      return finish(fixed ? QS_OK : QS_ERR_NOT_CONVERGED);
     }
     if (ir) {
       // correction e solves A e = r / scale_used in FP32; x += scale_used e
-      LevelBufs& l0 = hd->L[0];
+      // is made by the next residual
       const bool skip_fill = hd->p.n_pre >= 1 && hd->nlev > 1 && use_row_sweep<float>(hd, 0);
       if (!skip_fill) launch_fill<float>(l0.x32, l0.d.elems(), 0.0f, hd->stream);
       vcycle<float>(hd, 0, l0.x32, l0.b32, skip_fill);
-      launch_ir_update(x, l0.x32, d0, scale_used, hd->stream);
+      pending = true;
+      e_scale = scale_used;
     } else {
       vcycle<double>(hd, 0, x, b);
     }
     ++cycles;
   }
   inf->cycles = cycles;
-  return launch_check();
+  return finish(launch_check());
 }
 
 // Kernels that move column pairs as one two-wide access need 16-byte aligned

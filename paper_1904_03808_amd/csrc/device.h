@@ -68,6 +68,12 @@ template <typename Tin, typename Tout>
 int launch_residual_fine_zm(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
                             double out_scale, double* partial, hipStream_t s);
 int resid_zmarch_blocks(Dims d);
+// The same for the refinement loop: x_out = x + es * e on the interior (x_out
+// must not be x), r = (b - K x_out) * out_scale in FP32, partial sums of the
+// unscaled r^2.  Returns the number of partial sums.
+int launch_update_residual_zm(const double* x, const float* e, double es, double* x_out,
+                              const double* b, float* r, Dims d, const FineCoef<double>& c,
+                              double out_scale, double* partial, hipStream_t s);
 // Fine level: bc = T^T (b - K x) on the interior coarse nodes, without
 // writing the fine residual (kernels_resid.hip).  nx, ny, nz even.
 template <typename T>
@@ -84,8 +90,6 @@ void launch_reduce_sum(const double* partial, int n, double* out, hipStream_t s)
 
 template <typename T>
 void launch_fill(T* x, size_t n, T value, hipStream_t s);
-// x interior (double) += scale * e (float), fine level.
-void launch_ir_update(double* x, const float* e, Dims d, double scale, hipStream_t s);
 // Zero the interior planes of a node vector.
 template <typename T>
 void launch_zero_interior(T* x, Dims d, hipStream_t s);

@@ -417,16 +417,6 @@ __global__ void k_fill(T* __restrict__ x, size_t n, T v) {
   for (; t < n; t += stride) x[t] = v;
 }
 
-__global__ __launch_bounds__(256) void k_ir_update(double* __restrict__ x, const float* __restrict__ e,
-                                                   int nx, int ny, int nz, double scale) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int P = nx * ny, per = P * (nz - 1);
-  if (t >= 3 * per) return;
-  const int c = t / per, rem = t - c * per;
-  const size_t o = static_cast<size_t>(c) * (nz + 1) * P + P + rem;
-  x[o] += scale * static_cast<double>(e[o]);
-}
-
 template <typename T>
 __global__ void k_gather(const T* __restrict__ b, double* __restrict__ out, int nx, int ny, int nz) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -548,11 +538,6 @@ void launch_fill(T* x, size_t n, T value, hipStream_t s) {
   hipLaunchKernelGGL(k_fill<T>, dim3(nb), dim3(256), 0, s, x, n, value);
 }
 
-void launch_ir_update(double* x, const float* e, Dims d, double scale, hipStream_t s) {
-  const long long total = 3LL * d.nx * d.ny * (d.nz - 1);
-  hipLaunchKernelGGL(k_ir_update, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, e, d.nx, d.ny,
-                     d.nz, scale);
-}
 
 template <typename T>
 void launch_zero_interior(T* x, Dims d, hipStream_t s) {

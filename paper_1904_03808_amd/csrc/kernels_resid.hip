@@ -32,12 +32,19 @@ __device__ __forceinline__ int slot_idx(int p, int c, int hy, int hx) {
   return (((p % 3) * 3 + c) * HY + hy) * HX + hx;
 }
 
-template <typename Tin, typename Tout>
+// UPD: the iterate is first advanced by a correction, x' = x + es * e (the
+// refinement step of FP32 V-cycles inside FP64), x' is written to x_out on
+// the interior nodes of the tile and segment, and the residual is that of x'.
+// Every workgroup forms x' on its halo itself (same arithmetic), so x' must
+// go to another buffer than x.
+template <typename Tin, typename Tout, bool UPD>
 __global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
                                                      const Tin* __restrict__ b,
                                                      Tout* __restrict__ r, ZmArgs a,
                                                      FineCoef<Tin> cf, Tin out_scale,
-                                                     double* __restrict__ partial) {
+                                                     double* __restrict__ partial,
+                                                     const float* __restrict__ e, double es,
+                                                     Tin* __restrict__ x_out) {
   __shared__ Tin ring[3 * 3 * HALO];
   __shared__ double red[4];
   const int wg = blockIdx.x;
@@ -76,7 +83,13 @@ __global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
     for (int u = 0; u < 2; ++u)
       if (u < hcount)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pre[u][c] = x[c * C + static_cast<size_t>(p) * P + hoff[u]];
+        for (int c = 0; c < 3; ++c) {
+          const size_t q = c * C + static_cast<size_t>(p) * P + hoff[u];
+          if constexpr (UPD)
+            pre[u][c] = x[q] + es * static_cast<double>(e[q]);
+          else
+            pre[u][c] = x[q];
+        }
   };
   auto store = [&](int p) {
 #pragma unroll
@@ -136,6 +149,12 @@ __global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
       const Tin r0 = bc[0] - (diag * X(0, 0, 0, 0) - off0) * cf.ih2;
       const Tin r1 = bc[1] - (diag * X(1, 0, 0, 0) - off1) * cf.ih2;
       const Tin r2 = bc[2] - (diag * X(2, 0, 0, 0) - off2) * cf.ih2;
+      if constexpr (UPD) {
+        const size_t o = static_cast<size_t>(p) * P + oown;
+        x_out[o] = X(0, 0, 0, 0);
+        x_out[C + o] = X(1, 0, 0, 0);
+        x_out[2 * C + o] = X(2, 0, 0, 0);
+      }
 #undef X
       sq += static_cast<double>(r0) * r0 + static_cast<double>(r1) * r1 + static_cast<double>(r2) * r2;
       if (r) {
@@ -374,8 +393,17 @@ int launch_residual_fine_zm(const Tin* x, const Tin* b, Tout* r, Dims d, const F
   cf.inv_diag = static_cast<Tin>(c.inv_diag);
   cf.ih2 = static_cast<Tin>(c.ih2);
   const ZmArgs a = zm_args(d);
-  hipLaunchKernelGGL((k_residual_zm<Tin, Tout>), dim3(8 * a.grid_per_xcd), dim3(256), 0, s, x, b,
-                     r, a, cf, static_cast<Tin>(out_scale), partial);
+  hipLaunchKernelGGL((k_residual_zm<Tin, Tout, false>), dim3(8 * a.grid_per_xcd), dim3(256), 0, s,
+                     x, b, r, a, cf, static_cast<Tin>(out_scale), partial, nullptr, 0.0, nullptr);
+  return a.real_wgs;
+}
+
+int launch_update_residual_zm(const double* x, const float* e, double es, double* x_out,
+                              const double* b, float* r, Dims d, const FineCoef<double>& c,
+                              double out_scale, double* partial, hipStream_t s) {
+  const ZmArgs a = zm_args(d);
+  hipLaunchKernelGGL((k_residual_zm<double, float, true>), dim3(8 * a.grid_per_xcd), dim3(256), 0,
+                     s, x, b, r, a, c, out_scale, partial, e, es, x_out);
   return a.real_wgs;
 }
 
