@@ -353,43 +353,72 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __
 
 // x(f) += sum_J w(f - 2J) e(J) over the (up to 8) coarse nodes around f.  One
 // thread per pair of fine columns (2I, 2I+1) of a row, which use the coarse
-// columns I and I+1; the pair is read and written as one two-wide access.
+// columns I and I+1, marching up a segment of coarse planes: for each coarse
+// plane it combines the (up to) four coarse values of the pair's x-y
+// neighbourhood once, then adds plane K alone to fine plane 2K and the mean
+// of planes K and K+1 to fine plane 2K+1.  Each coarse value is loaded by the
+// threads of the rows next to it, not by every fine node around it; the fine
+// pair is read and written as one two-wide access.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T* __restrict__ ec,
-                                                     int nxf, int nyf, int nzf) {
+                                                     int nxf, int nyf, int nzf, int kseg) {
   using V = typename Pair<T>::type;
   const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int total = nxc * nyf * (nzf - 1);
-  if (t >= total) return;
-  const int i0 = t % nxc, j = (t / nxc) % nyf, k = 1 + t / (nxc * nyf);
+  const int per = nxc * nyf;  // threads per segment
+  const int nseg = (nzc + kseg - 1) / kseg;
+  if (t >= per * nseg) return;
+  const int i0 = t % nxc, j = (t / nxc) % nyf, sg = t / per;
+  const int Ks = sg * kseg, Ke = min(Ks + kseg, nzc);  // coarse planes K: fine 2K, 2K+1
   const int Pf = nxf * nyf, Cf = (nzf + 1) * Pf;
   const int Pc = nxc * nyc, Cc = (nzc + 1) * Pc;
   const int i1 = i0 + 1 == nxc ? 0 : i0 + 1;
-  const int j0 = j >> 1, k0 = k >> 1;
+  const int j0 = j >> 1;
   const int j1 = (j & 1) ? (j0 + 1 == nyc ? 0 : j0 + 1) : j0;
-  const int k1 = (k & 1) ? k0 + 1 : k0;
-  const bool oy = j & 1, oz = k & 1;
-  const T wy = oy ? T(0.5) : T(1), wz = oz ? T(0.5) : T(1);
-  const size_t o = static_cast<size_t>(k) * Pf + static_cast<size_t>(j) * nxf + 2 * i0;
+  const bool oy = j & 1;
+  const T wy = oy ? T(0.5) : T(1), wz = T(0.5);
+  // x-y combination of coarse plane K for the even and the odd fine column
+  auto coarse = [&](int K, T pe[3], T po[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T* E = ec + c * Cc;
-    // even fine column: e(i0); odd fine column: (e(i0) + e(i1)) / 2
-    auto row_e = [&](int kk, int jj) { return E[kk * Pc + jj * nxc + i0]; };
-    auto row_o = [&](int kk, int jj) {
-      const T* p = E + kk * Pc + jj * nxc;
-      return T(0.5) * (p[i0] + p[i1]);
-    };
-    auto plane_e = [&](int kk) { return oy ? wy * (row_e(kk, j0) + row_e(kk, j1)) : row_e(kk, j0); };
-    auto plane_o = [&](int kk) { return oy ? wy * (row_o(kk, j0) + row_o(kk, j1)) : row_o(kk, j0); };
-    const T add_e = oz ? wz * (plane_e(k0) + plane_e(k1)) : plane_e(k0);
-    const T add_o = oz ? wz * (plane_o(k0) + plane_o(k1)) : plane_o(k0);
-    V* px = reinterpret_cast<V*>(x + c * Cf + o);
-    V v = *px;
-    v.x += add_e;
-    v.y += add_o;
-    *px = v;
+    for (int c = 0; c < 3; ++c) {
+      const T* p0 = ec + c * Cc + K * Pc + j0 * nxc;
+      const T a0 = p0[i0], a1 = p0[i1];
+      if (oy) {
+        const T* p1 = ec + c * Cc + K * Pc + j1 * nxc;
+        const T b0 = p1[i0], b1 = p1[i1];
+        pe[c] = wy * (a0 + b0);
+        po[c] = wy * (T(0.5) * (a0 + a1) + T(0.5) * (b0 + b1));
+      } else {
+        pe[c] = a0;
+        po[c] = T(0.5) * (a0 + a1);
+      }
+    }
+  };
+  T pe0[3], po0[3], pe1[3], po1[3];
+  coarse(Ks, pe0, po0);
+  const size_t orow = static_cast<size_t>(j) * nxf + 2 * i0;
+  for (int K = Ks; K < Ke; ++K) {
+    coarse(K + 1, pe1, po1);  // K + 1 <= nzc (the top coarse wall is zero)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (K >= 1) {  // fine plane 2K (plane 0 is the wall)
+        V* px = reinterpret_cast<V*>(x + c * Cf + static_cast<size_t>(2 * K) * Pf + orow);
+        V v = *px;
+        v.x += pe0[c];
+        v.y += po0[c];
+        *px = v;
+      }
+      V* qx = reinterpret_cast<V*>(x + c * Cf + static_cast<size_t>(2 * K + 1) * Pf + orow);
+      V v = *qx;
+      v.x += wz * (pe0[c] + pe1[c]);
+      v.y += wz * (po0[c] + po1[c]);
+      *qx = v;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pe0[c] = pe1[c];
+      po0[c] = po1[c];
+    }
   }
 }
 
@@ -521,10 +550,18 @@ void launch_restrict(const T* r, T* bc, Dims f, hipStream_t s) {
 
 template <typename T>
 void launch_prolong_add(T* x, const T* ec, Dims f, hipStream_t s) {
-  const long long total = static_cast<long long>(f.nx / 2) * f.ny * (f.nz - 1);
+  // march just far enough that the launch keeps about 512K threads: a long
+  // march reloads fewer coarse values, a short one exposes less latency per
+  // thread (small levels)
+  const int nzc = f.nz / 2;
+  if (nzc <= 0) return;
+  const long long per = static_cast<long long>(f.nx / 2) * f.ny;
+  const long long want = std::max<long long>(1, (512 * 1024 + per - 1) / per);
+  const int kseg = static_cast<int>(std::max<long long>(1, (nzc + want - 1) / want));
+  const long long total = per * ((nzc + kseg - 1) / kseg);
   if (total <= 0) return;
   hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, ec, f.nx,
-                     f.ny, f.nz);
+                     f.ny, f.nz, kseg);
 }
 
 void launch_reduce_sum(const double* partial, int n, double* out, hipStream_t s) {
