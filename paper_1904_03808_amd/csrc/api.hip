@@ -279,8 +279,19 @@ void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse,
   LevelBufs& lb = hd->L[l];
   const int* ord = hd->p.colour_order;
   if (!use_row_sweep<T>(hd, l)) {
+    // on the coarse levels, consecutive colours that differ only in the x
+    // parity share one launch
+    const bool pairs = l > 0 && colour_pair_supported(lb.d);
     for (int s = 0; s < sweeps; ++s)
-      for (int q = 0; q < 8; ++q) colour_pass<T>(hd, l, x, b, ord[reverse ? 7 - q : q]);
+      for (int q = 0; q < 8; ++q) {
+        const int c = ord[reverse ? 7 - q : q];
+        if (pairs && q % 2 == 0 && ord[reverse ? 6 - q : q + 1] == (c ^ 1)) {
+          launch_colour_pair_gen<T>(x, b, lb.d, c, Prec<T>::S(lb), Prec<T>::D(lb), hd->stream);
+          ++q;
+          continue;
+        }
+        colour_pass<T>(hd, l, x, b, c);
+      }
     return;
   }
   // y's wall planes are zero from setup (coarse levels, FP32 corrections) or

@@ -33,6 +33,12 @@ void launch_colour_fine(T* x, const T* b, Dims d, int colour, const FineCoef<T>&
 template <typename T>
 void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
                        hipStream_t s);
+// Colours c and c ^ 1 (c first) in one launch on a level with the generic
+// stencil; needs an even row length of at most 512.
+template <typename T>
+void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
+                            hipStream_t s);
+bool colour_pair_supported(Dims d);
 
 // Fine-level row-parity half sweep (kernels_sweep.hip): updates every node
 // of the rows with parity row_par, reading own rows from own_src, neighbour

@@ -308,6 +308,128 @@ struct Pair<double> {
   using type = double2;
 };
 
+// Two colours that differ only in the x parity, (a, b) = (c, c ^ 1) with c
+// first, in one launch on a coarse level.  Nodes of colour a couple to nodes
+// of colour b only along x within their row and plane, so a thread owns the
+// column pair (2p, 2p+1) of one row and plane: it updates its a-node from the
+// old values, then its b-node once both x neighbours of colour a (its own and
+// the one of pair p+1 or p-1) are new.  Those come through LDS; a workgroup
+// holds whole rows, so the periodic neighbour in x is always present.  Every
+// other term of the b-node uses values that neither update changes, and is
+// summed while the a-node is.  Neighbour values of both nodes are read as
+// pairs plus the two outer columns (four columns per row), so a launch moves
+// half the loads of two single-colour launches.
+template <typename T, int XF>
+__global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, const T* __restrict__ b,
+                                                         int nx, int ny, int nz, ColourRange cr,
+                                                         int rows_per_block,
+                                                         const T* __restrict__ S,
+                                                         const T* __restrict__ Dinv) {
+  using V = typename Pair<T>::type;
+  __shared__ T sc[252];
+  __shared__ T xa[3][256];
+  const int W = nx / 2;  // column pairs per row
+  const int tid = threadIdx.x;
+  const int rr = tid / W, p = tid - rr * W;
+  const int jj = blockIdx.x * rows_per_block + rr;
+  const bool active = rr < rows_per_block && jj < cr.hy;
+  const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
+  stage_stencil_inverse<T>(sc, S, Dinv, k);
+  constexpr int xf = XF;  // x parity of the colour updated first (cr.a)
+  const int j = 2 * (active ? jj : 0) + cr.bb;
+  const int i0 = 2 * p;
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int il = i0 == 0 ? nx - 1 : i0 - 1;       // column i0-1
+  const int ir = i0 + 2 == nx ? 0 : i0 + 2;       // column i0+2
+  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
+  const int o = k * P + j * nx + i0;
+  T acca[3], accb[3];
+  {
+    V bv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bv[c] = *reinterpret_cast<const V*>(b + c * C + o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      acca[c] = xf ? bv[c].y : bv[c].x;
+      accb[c] = xf ? bv[c].x : bv[c].y;
+    }
+  }
+  __syncthreads();
+  // columns of the four-wide window: w[0] = i0-1, w[1] = i0, w[2] = i0+1,
+  // w[3] = i0+2; the node at column i0 + s uses w[s .. s+2]
+  constexpr int sa = xf, sb = 1 - xf;
+  T side[2][3];  // b-node's x neighbours in its own row and plane, summed last
+#pragma unroll 1
+  for (int oz = 0; oz < 3; ++oz) {
+    const int kk = k + oz - 1;
+    T w[3][4][3];
+#pragma unroll
+    for (int y = 0; y < 3; ++y) {
+      const int row = kk * P + ys[y] * nx;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const V v = *reinterpret_cast<const V*>(x + c * C + row + i0);
+        w[y][1][c] = v.x;
+        w[y][2][c] = v.y;
+        w[y][0][c] = x[c * C + row + il];
+        w[y][3][c] = x[c * C + row + ir];
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < 3; ++y) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const T* B = sc + (oz * 9 + y * 3 + q) * 9;
+        if (oz == 1 && y == 1) {
+          if (q == 1) continue;  // centre blocks
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            accb[c] -= B[c * 3] * w[y][q + sb][0] + B[c * 3 + 1] * w[y][q + sb][1] +
+                       B[c * 3 + 2] * w[y][q + sb][2];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          acca[c] -= B[c * 3] * w[y][q + sa][0] + B[c * 3 + 1] * w[y][q + sa][1] +
+                     B[c * 3 + 2] * w[y][q + sa][2];
+      }
+    }
+  }
+  const T* Di = sc + 243;
+  T na[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) na[c] = Di[c * 3] * acca[0] + Di[c * 3 + 1] * acca[1] + Di[c * 3 + 2] * acca[2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
+  __syncthreads();
+  // the b-node's x neighbours of colour a: own a-node and that of the pair on
+  // the side away from it
+  const int pn = xf ? (p == 0 ? W - 1 : p - 1) : (p == W - 1 ? 0 : p + 1);
+  const int tn = active ? rr * W + pn : tid;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    side[xf][c] = na[c];       // xf = 0: left neighbour (i0) is own; xf = 1: right (i0+1)
+    side[1 - xf][c] = xa[c][tn];
+  }
+  {
+    const T* Bl = sc + (9 + 3 + 0) * 9;  // oz = 1, y = 1, q = 0: x - 1
+    const T* Br = sc + (9 + 3 + 2) * 9;  // q = 2: x + 1
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      accb[c] -= Bl[c * 3] * side[0][0] + Bl[c * 3 + 1] * side[0][1] + Bl[c * 3 + 2] * side[0][2] +
+                 (Br[c * 3] * side[1][0] + Br[c * 3 + 1] * side[1][1] + Br[c * 3 + 2] * side[1][2]);
+  }
+  if (!active) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T nb = Di[c * 3] * accb[0] + Di[c * 3 + 1] * accb[1] + Di[c * 3 + 2] * accb[2];
+    V v;
+    v.x = xf ? nb : na[c];
+    v.y = xf ? na[c] : nb;
+    *reinterpret_cast<V*>(x + c * C + o) = v;
+  }
+}
+
 // b_c(I) = sum over the 27 fine nodes around 2I of w * r(f), w = prod (1 or 1/2).
 // One thread per coarse node; per fine row it loads the pair (2I, 2I+1) as one
 // two-wide access and takes 2I-1 from the lane to its left (a separate load
@@ -500,6 +622,26 @@ void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T
                      d.nx, d.ny, d.nz, cr, S, Dinv);
 }
 
+bool colour_pair_supported(Dims d) { return d.nx % 2 == 0 && d.nx >= 2 && d.nx <= 512; }
+
+template <typename T>
+void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
+                            hipStream_t s) {
+  // colour is the one updated first; its partner is colour ^ 1
+  const ColourRange cr = colour_range(d, colour);
+  if (cr.total() <= 0) return;
+  const int W = d.nx / 2;
+  const int rpb = std::max(1, std::min(cr.hy, 256 / W));
+  const int threads = (rpb * W + 63) / 64 * 64;
+  const dim3 grid(blocks_for(cr.hy, rpb), cr.nk);
+  if (cr.a)
+    hipLaunchKernelGGL((k_colour_pair_gen<T, 1>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
+                       cr, rpb, S, Dinv);
+  else
+    hipLaunchKernelGGL((k_colour_pair_gen<T, 0>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
+                       cr, rpb, S, Dinv);
+}
+
 int residual_blocks(Dims d) {
   const int flat = blocks_for(static_cast<long long>(d.nx) * d.ny * (d.nz - 1), kReduceBlock);
   const int planes = blocks_for(static_cast<long long>(d.nx) * d.ny, kReduceBlock) * (d.nz - 1);
@@ -595,6 +737,8 @@ void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, do
 #define QS_INST(T)                                                                               \
   template void launch_colour_fine<T>(T*, const T*, Dims, int, const FineCoef<T>&, hipStream_t); \
   template void launch_colour_gen<T>(T*, const T*, Dims, int, const T*, const T*, hipStream_t);  \
+  template void launch_colour_pair_gen<T>(T*, const T*, Dims, int, const T*, const T*,           \
+                                          hipStream_t);                                          \
   template int launch_residual_gen<T>(const T*, const T*, T*, Dims, const T*, bool, double*,     \
                                       hipStream_t);                                              \
   template void launch_restrict<T>(const T*, T*, Dims, hipStream_t);                             \

@@ -235,8 +235,32 @@ def test_row_sweep_matches_oracle(n, mc, prec):
             assert rel(host(xd).astype(np.float64), xr) < tol, (level, sweeps)
 
 
+@pytest.mark.parametrize("n,mc", [((160, 24, 16), 4), ((64, 64, 64), 8)])
+@pytest.mark.parametrize("order", [ROW, (7, 6, 3, 2, 5, 4, 1, 0), (1, 0, 3, 2, 5, 4, 7, 6),
+                                   (2, 3, 0, 1, 6, 7, 4, 5)])
+def test_paired_colour_sweeps(n, mc, order):
+    """On coarse levels two colours that differ only in the x parity and follow
+    each other in the order share one launch, with either parity first; whole
+    sweeps match the oracle's colour-by-colour sweep (rows of 80 and 32 nodes,
+    six and sixteen rows per workgroup), for 1 and 3 sweeps."""
+    rng = np.random.default_rng(12)
+    g, o = make(*n, min_coarse_nz=mc, colour_order=order)
+    for level in range(1, g.levels - 1):
+        L = o.levels[level]
+        x = rand_node(rng, L.nx, L.ny, L.nz, walls=False)
+        b = rand_node(rng, L.nx, L.ny, L.nz)
+        for sweeps in (1, 3):
+            xd = dev(x)
+            g.smooth(level, xd, dev(b), sweeps)
+            xr = x.copy()
+            for _ in range(sweeps):
+                L.sweep(xr, b, o.order)
+            assert rel(host(xd), xr) < 1e-13, (level, sweeps)
+
+
 def test_other_colour_order():
-    """Any colour permutation runs (one launch per colour) and matches the oracle."""
+    """A colour permutation with no two x-parity partners next to each other
+    runs one launch per colour on every level and matches the oracle."""
     rng = np.random.default_rng(7)
     order = [0, 4, 1, 5, 2, 6, 3, 7]
     g, o = make(32, 32, 32, colour_order=order)
