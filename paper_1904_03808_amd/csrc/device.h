@@ -27,6 +27,29 @@ struct FineCoef {
 
 constexpr int kReduceBlock = 256;
 
+// Two-wide loads and stores with the non-temporal hint, for data a launch
+// touches once (so that L2 keeps what neighbouring workgroups share).  V is
+// the two-wide HIP type of T (float2, double2).
+template <typename T>
+struct NT2 {
+  typedef T E __attribute__((ext_vector_type(2)));
+  template <typename V>
+  __device__ static __forceinline__ V load(const T* p) {
+    const E e = __builtin_nontemporal_load(reinterpret_cast<const E*>(p));
+    V v;
+    v.x = e.x;
+    v.y = e.y;
+    return v;
+  }
+  template <typename V>
+  __device__ static __forceinline__ void store(T* p, const V& v) {
+    E e;
+    e.x = v.x;
+    e.y = v.y;
+    __builtin_nontemporal_store(e, reinterpret_cast<E*>(p));
+  }
+};
+
 // --- multigrid kernels (kernels_mg.hip) -----------------------------------
 template <typename T>
 void launch_colour_fine(T* x, const T* b, Dims d, int colour, const FineCoef<T>& c, hipStream_t s);

@@ -524,17 +524,17 @@ __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T*
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (K >= 1) {  // fine plane 2K (plane 0 is the wall)
-        V* px = reinterpret_cast<V*>(x + c * Cf + static_cast<size_t>(2 * K) * Pf + orow);
-        V v = *px;
+        T* px = x + c * Cf + static_cast<size_t>(2 * K) * Pf + orow;
+        V v = NT2<T>::template load<V>(px);
         v.x += pe0[c];
         v.y += po0[c];
-        *px = v;
+        NT2<T>::store(px, v);
       }
-      V* qx = reinterpret_cast<V*>(x + c * Cf + static_cast<size_t>(2 * K + 1) * Pf + orow);
-      V v = *qx;
+      T* qx = x + c * Cf + static_cast<size_t>(2 * K + 1) * Pf + orow;
+      V v = NT2<T>::template load<V>(qx);
       v.x += wz * (pe0[c] + pe1[c]);
       v.y += wz * (po0[c] + po1[c]);
-      *qx = v;
+      NT2<T>::store(qx, v);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

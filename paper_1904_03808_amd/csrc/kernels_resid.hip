@@ -6,8 +6,10 @@
 // workgroup (the halo columns once more by the neighbouring tile, usually
 // from L2); the next plane is fetched into registers while the current one
 // is computed.  The squared residual is summed per workgroup in double for
-// the convergence test.  Tiles are ordered so that each XCD takes a
-// contiguous block of them (neighbouring tiles share halos through its L2).
+// the convergence test.  b and the outputs are touched once and carry the
+// non-temporal hint, which leaves L2 to the shared halo of x.  Tiles are
+// ordered so that each XCD takes a contiguous block of them (neighbouring
+// tiles share halos through its L2).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -105,7 +107,8 @@ __global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
   auto fetch_b = [&](int p, Tin out[3]) {
     if (b && own && p >= 1 && p <= nz - 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) out[c] = b[c * C + static_cast<size_t>(p) * P + oown];
+      for (int c = 0; c < 3; ++c)
+        out[c] = __builtin_nontemporal_load(b + c * C + static_cast<size_t>(p) * P + oown);
     }
   };
 
@@ -151,17 +154,17 @@ __global__ __launch_bounds__(256) void k_residual_zm(const Tin* __restrict__ x,
       const Tin r2 = bc[2] - (diag * X(2, 0, 0, 0) - off2) * cf.ih2;
       if constexpr (UPD) {
         const size_t o = static_cast<size_t>(p) * P + oown;
-        x_out[o] = X(0, 0, 0, 0);
-        x_out[C + o] = X(1, 0, 0, 0);
-        x_out[2 * C + o] = X(2, 0, 0, 0);
+        __builtin_nontemporal_store(X(0, 0, 0, 0), x_out + o);
+        __builtin_nontemporal_store(X(1, 0, 0, 0), x_out + C + o);
+        __builtin_nontemporal_store(X(2, 0, 0, 0), x_out + 2 * C + o);
       }
 #undef X
       sq += static_cast<double>(r0) * r0 + static_cast<double>(r1) * r1 + static_cast<double>(r2) * r2;
       if (r) {
         const size_t o = static_cast<size_t>(p) * P + oown;
-        r[o] = static_cast<Tout>(r0 * out_scale);
-        r[C + o] = static_cast<Tout>(r1 * out_scale);
-        r[2 * C + o] = static_cast<Tout>(r2 * out_scale);
+        __builtin_nontemporal_store(static_cast<Tout>(r0 * out_scale), r + o);
+        __builtin_nontemporal_store(static_cast<Tout>(r1 * out_scale), r + C + o);
+        __builtin_nontemporal_store(static_cast<Tout>(r2 * out_scale), r + 2 * C + o);
       }
     }
 #pragma unroll
@@ -276,7 +279,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(const T* __restrict__ x,
     for (int u = 0; u < 3; ++u)
       if (tid + u * 256 < RN)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[u][c] = b[c * C + static_cast<size_t>(p) * P + roff[u]];
+        for (int c = 0; c < 3; ++c)
+          out[u][c] = __builtin_nontemporal_load(b + c * C + static_cast<size_t>(p) * P + roff[u]);
   };
 
   const int kf0 = 2 * K0 - 1, kf1 = 2 * K1 - 1;  // fine planes of the march

@@ -128,7 +128,7 @@ __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __rest
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     out.v[k] = Z >= 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + om);
-    out.v[3 + k] = Z >= 1 ? zero : *reinterpret_cast<const V*>(own_src + k * c.C + oo);
+    out.v[3 + k] = Z >= 1 ? zero : NT2<T>::template load<V>(own_src + k * c.C + oo);
   }
   if (top) {
 #pragma unroll
@@ -167,7 +167,7 @@ __device__ __forceinline__ void fetch_b(const Ctx<T, NX>& c, const T* __restrict
   const int nx = NX > 0 ? NX : c.nx;
   const size_t o = static_cast<size_t>(p) * c.P + static_cast<size_t>(c.j) * nx + c.c0;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) out[k] = *reinterpret_cast<const V*>(b + k * c.C + o);
+  for (int k = 0; k < 3; ++k) out[k] = NT2<T>::template load<V>(b + k * c.C + o);
 }
 
 // Gauss-Seidel value of the node (row j, plane p, column col):
@@ -245,7 +245,7 @@ __device__ __forceinline__ void update_plane(const Ctx<T, NX>& c, int p, int z0,
       V v;
       v.x = X1 ? ob[k] : oa[k];
       v.y = X1 ? oa[k] : ob[k];
-      *reinterpret_cast<V*>(dst + k * c.C + o) = v;
+      NT2<T>::store(dst + k * c.C + o, v);
     }
   }
 }
