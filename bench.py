@@ -28,14 +28,14 @@ HBM_PEAK_GBS = 8000.0
 # counter runs of `bench.py --profile-smoother` (FETCH_SIZE, then WRITE_SIZE; KiB
 # per dispatch, mean of 6 launches).  A 512 MiB device copy reads as
 # FETCH_SIZE = 262,166 KiB and WRITE_SIZE = 524,288 KiB: on this chip every read
-# request (TCC_EA0_RDREQ, 4,194,587 for the copy) carries 128 bytes but the
+# request (TCC_EA0_RDREQ, 4,194,593 for the copy) carries 128 bytes but the
 # derived FETCH_SIZE prices it at 64, so reads scale by 2.0 and writes by 1.0.
 # Valid only for the kernel source these counters were taken on.
 SWEEP_COUNTERS = {
     "kernel_source": "paper_1904_03808_amd/csrc/kernels_sweep.hip",
-    "source_sha256_16": "248d85a99392c368",
+    "source_sha256_16": "5bae76a0193c3cd7",
     "n": 256,
-    "fetch_kib": 178548.0,
+    "fetch_kib": 177897.4,
     "write_kib": 97920.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
