@@ -262,6 +262,14 @@ def main():
     algo_bytes = 36.0 * nodes / 2
     achieved = algo_bytes / (sm["fp32"]["avg_launch_us"] * 1e-6) / 1e9
     traffic = sweep_traffic(n)
+    # measured streaming reference: a 1 GiB device-to-device tensor copy
+    # (read + write bytes over its event time)
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    copy_ms = _events_ms(lambda: dst.copy_(src), 10)
+    copy_gbs = 2.0 * src.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del src, dst
     out = {
         "metric": METRIC,
         "value": results["fp32_ir"]["solves_per_s"],
@@ -288,7 +296,8 @@ def main():
         "smoother": sm,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_sweep_rows<float, 256>: fine-level FP32 half sweep",
+                     "kernel": "k_sweep_rows<float, 256, 0, 0>: fine-level FP32 half sweep",
+                     "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "algorithmic_bytes_per_launch": algo_bytes,
                      "bytes_per_node_update": 36,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE)",
