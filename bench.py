@@ -153,6 +153,80 @@ def config_512(steps: int = 3, warmup: int = 1) -> dict:
     return out
 
 
+def config3_shear(n: int = 256, steps: int = 20) -> dict:
+    """Quasi-static steps under simple shear: `steps` FP32-IR projection steps at
+    n^3 from the shear initial state (chi seed 3), warm-started from the
+    previous velocity, timed between device synchronisations; then the phases
+    of one more step (STZ update, right-hand side, solve, stress correction)
+    timed one by one with HIP events on the library's stream."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, shear_state, stz_constants
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    P, dt, U = stz_constants(), 10.0, 1e-5
+    st = shear_state(n, n, n, seed=3, U=U)
+    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp32-ir", device=dev)
+    v0, s0, c0 = (torch.from_numpy(st[k]).to(dev) for k in ("v", "sigma", "chi"))
+    del st
+    v, s, c = v0.clone(), s0.clone(), c0.clone()
+    g.projection_step(P, dt, U, v, s, c, rtol=1e-10)  # warm-up (state discarded)
+    v.copy_(v0), s.copy_(s0), c.copy_(c0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = [g.projection_step(P, dt, U, v, s, c, rtol=1e-10).cycles for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ph = {}
+    ph["stz_ms"] = _events_ms(lambda: g.stz_step(P, dt, v, s, c), 3)
+    sstar, _ = g.stz_step(P, dt, v, s, c)
+    ph["rhs_ms"] = _events_ms(lambda: g.rhs(sstar, dt), 3)
+    b = g.rhs(sstar, dt)
+    x = v.clone()
+    ph["solve_ms"] = _events_ms(lambda: (x.copy_(v), g.solve(b, x, rtol=1e-10)), 1)
+    ph["stress_update_ms"] = _events_ms(lambda: g.stress_update(sstar, x, dt), 3)
+    g.close()
+    del v0, s0, c0, v, s, c, sstar, b, x
+    torch.cuda.empty_cache()
+    return {"grid": [n, n, n], "steps": steps, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
+            "cycles_per_step": cycles, "phase_ms_one_step": ph, "solver": "fp32-ir",
+            "inputs": "shear state: sigma_xz = 0.99 s_Y, linear v, chi Gaussian field (seed 3)"}
+
+
+def config4_adjoint(n: int = 96, steps: int = 10) -> dict:
+    """Reverse mode of a `steps`-step FP64 rollout at n^3 (chi seed 4): time of
+    the forward pass with per-step checkpoints and of the backward pass (the
+    transposed solves and the step VJPs), solves to 1e-10."""
+    import torch
+
+    from paper_1904_03808_amd.autograd import rollout_loss
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, shear_state, stz_constants
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    P, dt, U = stz_constants(), 10.0, 1e-5
+    st = shear_state(n, n, n, seed=4, U=U)
+    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp64", device=dev)
+    v0, s0, c0 = (torch.from_numpy(st[k]).to(dev) for k in ("v", "sigma", "chi"))
+    times = []
+    for _ in range(2):  # the first pass is a warm-up
+        chi = c0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = rollout_loss(chi, v0, s0, g, P, dt, U, steps, rtol=1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    g.close()
+    return {"grid": [n, n, n], "steps": steps, "forward_ms": times[-1][0],
+            "backward_ms": times[-1][1], "gradient_ms": sum(times[-1]),
+            "loss": loss.item(), "solver": "fp64, rtol 1e-10 forward and transposed"}
+
+
 def profile_smoother(n: int) -> None:
     """Kernels for hardware-counter runs: one device-to-device copy of a known
     size (calibrates FETCH_SIZE / WRITE_SIZE), then 3 fine-level sweeps in FP32
@@ -189,6 +263,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 comparison block")
+    ap.add_argument("--no-steps", action="store_true",
+                    help="skip the shear-step (256^3) and adjoint (96^3) blocks")
     ap.add_argument("--profile-smoother", action="store_true",
                     help="only run a calibration copy and fine-level sweeps (for rocprofv3 counters)")
     args = ap.parse_args()
@@ -306,6 +382,9 @@ def main():
     }
     if not args.no_512 and n == 256:
         out["config2_512"] = config_512()
+    if not args.no_steps and n == 256:
+        out["config3_shear_256"] = config3_shear()
+        out["config4_adjoint_96"] = config4_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, results["fp64"]["cycles"])
     print(json.dumps(out))
