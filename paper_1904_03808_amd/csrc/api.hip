@@ -326,14 +326,15 @@ void vcycle(qs_handle* hd, int l, T* x, const T* b, bool x_zero = false) {
   }
   smooth<T>(hd, l, x, b, hd->p.n_pre, false, x_zero);
   LevelBufs& cb = hd->L[l + 1];
+  // the restriction also clears the interior of the coarse correction (its
+  // walls are zero from setup and never written)
   if (l == 0) {
-    launch_resid_restrict<T>(x, b, Prec<T>::b(cb), lb.d, hd->fc64, hd->stream);
+    launch_resid_restrict<T>(x, b, Prec<T>::b(cb), Prec<T>::x(cb), lb.d, hd->fc64, hd->stream);
   } else {
     T* r = Prec<T>::r(lb);
     residual<T>(hd, l, x, b, r, false);
-    launch_restrict<T>(r, Prec<T>::b(cb), lb.d, hd->stream);
+    launch_restrict<T>(r, Prec<T>::b(cb), Prec<T>::x(cb), lb.d, hd->stream);
   }
-  launch_fill<T>(Prec<T>::x(cb), cb.d.elems(), T(0), hd->stream);
   vcycle<T>(hd, l + 1, Prec<T>::x(cb), Prec<T>::b(cb));
   launch_prolong_add<T>(x, Prec<T>::x(cb), lb.d, hd->stream);
   smooth<T>(hd, l, x, b, hd->p.n_post, true);
@@ -457,9 +458,12 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
     }
     if (lb.y64) launch_fill<double>(lb.y64, lb.d.elems(), 0.0, hd->stream);
     if (lb.y32) launch_fill<float>(lb.y32, lb.d.elems(), 0.0f, hd->stream);
-    // the FP32 correction of the fine level: walls stay zero for good (the
-    // refinement loop may skip clearing its interior, see solve_impl)
+    // the FP32 correction of the fine level and the coarse-level corrections:
+    // walls stay zero for good (the refinement loop may skip clearing the
+    // fine interior, see solve_impl; the restriction clears coarse interiors)
     if (l == 0 && lb.x32) launch_fill<float>(lb.x32, lb.d.elems(), 0.0f, hd->stream);
+    if (l > 0 && lb.x32) launch_fill<float>(lb.x32, lb.d.elems(), 0.0f, hd->stream);
+    if (l > 0 && lb.x64) launch_fill<double>(lb.x64, lb.d.elems(), 0.0, hd->stream);
   }
   // upload stencils (FP64 and their FP32 roundings) and the coarse inverse;
   // the staging vectors live until the synchronisation below
@@ -767,7 +771,7 @@ qs_status qs_level_residual(qs_handle* hd, int level, const double* x, const dou
 qs_status qs_level_restrict(qs_handle* hd, int level, const double* r, double* b_coarse) {
   if (!hd || level < 0 || level >= hd->nlev - 1 || !r || !b_coarse || !aligned16(r))
     return QS_ERR_ARG;
-  launch_restrict<double>(r, b_coarse, hd->L[level].d, hd->stream);
+  launch_restrict<double>(r, b_coarse, nullptr, hd->L[level].d, hd->stream);
   return launch_check();
 }
 

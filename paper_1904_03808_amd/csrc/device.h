@@ -104,13 +104,15 @@ int launch_update_residual_zm(const double* x, const float* e, double es, double
                               const double* b, float* r, Dims d, const FineCoef<double>& c,
                               double out_scale, double* partial, hipStream_t s);
 // Fine level: bc = T^T (b - K x) on the interior coarse nodes, without
-// writing the fine residual (kernels_resid.hip).  nx, ny, nz even.
+// writing the fine residual (kernels_resid.hip).  nx, ny, nz even.  With xc
+// non-null, the coarse correction is cleared at the same interior nodes.
 template <typename T>
-void launch_resid_restrict(const T* x, const T* b, T* bc, Dims d, const FineCoef<double>& c,
-                           hipStream_t s);
+void launch_resid_restrict(const T* x, const T* b, T* bc, T* xc, Dims d,
+                           const FineCoef<double>& c, hipStream_t s);
 
+// bc = T^T r; with xc non-null, also xc = 0 at the interior coarse nodes.
 template <typename T>
-void launch_restrict(const T* r, T* bc, Dims fine, hipStream_t s);
+void launch_restrict(const T* r, T* bc, T* xc, Dims fine, hipStream_t s);
 template <typename T>
 void launch_prolong_add(T* x, const T* ec, Dims fine, hipStream_t s);
 

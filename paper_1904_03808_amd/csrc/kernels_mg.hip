@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
 // only on the first lane of a wave or of a row).
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __restrict__ bc,
-                                                  int nxf, int nyf, int nzf) {
+                                                  T* __restrict__ xc, int nxf, int nyf, int nzf) {
   using V = typename Pair<T>::type;
   const int nxc = nxf / 2, nyc = nyf / 2, nzc = nzf / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -469,7 +469,10 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __
       }
       acc += w[dz] * az;
     }
-    if (act) bc[c * Cc + K * Pc + J * nxc + I] = acc;
+    if (act) {
+      bc[c * Cc + K * Pc + J * nxc + I] = acc;
+      if (xc) xc[c * Cc + K * Pc + J * nxc + I] = T(0);
+    }
   }
 }
 
@@ -683,10 +686,10 @@ int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool z
 }
 
 template <typename T>
-void launch_restrict(const T* r, T* bc, Dims f, hipStream_t s) {
+void launch_restrict(const T* r, T* bc, T* xc, Dims f, hipStream_t s) {
   const long long total = static_cast<long long>(f.nx / 2) * (f.ny / 2) * (f.nz / 2 - 1);
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, r, bc, f.nx,
+  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, r, bc, xc, f.nx,
                      f.ny, f.nz);
 }
 
@@ -741,7 +744,7 @@ void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, do
                                           hipStream_t);                                          \
   template int launch_residual_gen<T>(const T*, const T*, T*, Dims, const T*, bool, double*,     \
                                       hipStream_t);                                              \
-  template void launch_restrict<T>(const T*, T*, Dims, hipStream_t);                             \
+  template void launch_restrict<T>(const T*, T*, T*, Dims, hipStream_t);                         \
   template void launch_prolong_add<T>(T*, const T*, Dims, hipStream_t);                          \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                      \
   template void launch_zero_interior<T>(T*, Dims, hipStream_t);                                  \

@@ -218,8 +218,8 @@ struct RrArgs {
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict(const T* __restrict__ x,
                                                         const T* __restrict__ b,
-                                                        T* __restrict__ bc, RrArgs a,
-                                                        FineCoef<T> cf) {
+                                                        T* __restrict__ bc, T* __restrict__ xc,
+                                                        RrArgs a, FineCoef<T> cf) {
   __shared__ T ring[3 * 3 * XN];  // [plane % 3][component][XYN][XXN]
   __shared__ T rp[3 * RN];        // residual of the current plane [component][RYN][RXN]
   const int wg = blockIdx.x;
@@ -355,6 +355,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(const T* __restrict__ x,
           if (kf > kf0) {
             acc[c] += w[2] * az;
             bc[c * Cc + static_cast<size_t>(Kdone) * Pc + ob] = acc[c];
+            if (xc) xc[c * Cc + static_cast<size_t>(Kdone) * Pc + ob] = T(0);
           }
           acc[c] = T(0) + w[0] * az;
         } else {
@@ -412,8 +413,8 @@ int launch_update_residual_zm(const double* x, const float* e, double es, double
 }
 
 template <typename T>
-void launch_resid_restrict(const T* x, const T* b, T* bc, Dims d, const FineCoef<double>& c,
-                           hipStream_t s) {
+void launch_resid_restrict(const T* x, const T* b, T* bc, T* xc, Dims d,
+                           const FineCoef<double>& c, hipStream_t s) {
   if (d.nz / 2 - 1 <= 0) return;
   FineCoef<T> cf;
   cf.h2 = static_cast<T>(c.h2);
@@ -423,13 +424,13 @@ void launch_resid_restrict(const T* x, const T* b, T* bc, Dims d, const FineCoef
   cf.inv_diag = static_cast<T>(c.inv_diag);
   cf.ih2 = static_cast<T>(c.ih2);
   const RrArgs a = rr_args(d);
-  hipLaunchKernelGGL((k_resid_restrict<T>), dim3(8 * a.grid_per_xcd), dim3(256), 0, s, x, b, bc, a,
-                     cf);
+  hipLaunchKernelGGL((k_resid_restrict<T>), dim3(8 * a.grid_per_xcd), dim3(256), 0, s, x, b, bc, xc,
+                     a, cf);
 }
 
-template void launch_resid_restrict<double>(const double*, const double*, double*, Dims,
+template void launch_resid_restrict<double>(const double*, const double*, double*, double*, Dims,
                                             const FineCoef<double>&, hipStream_t);
-template void launch_resid_restrict<float>(const float*, const float*, float*, Dims,
+template void launch_resid_restrict<float>(const float*, const float*, float*, float*, Dims,
                                            const FineCoef<double>&, hipStream_t);
 template int launch_residual_fine_zm<double, double>(const double*, const double*, double*, Dims,
                                                      const FineCoef<double>&, double, double*,
