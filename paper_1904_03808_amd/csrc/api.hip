@@ -213,6 +213,10 @@ void colour_pass(qs_handle* hd, int l, T* x, const T* b, int colour) {
     launch_colour_gen<T>(x, b, lb.d, colour, Prec<T>::S(lb), Prec<T>::D(lb), hd->stream);
 }
 
+// Kernels that move column pairs as one two-wide access need 16-byte aligned
+// node vectors (every device allocation is; an offset view may not be).
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <typename T>
 void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_interior) {
   LevelBufs& lb = hd->L[l];
@@ -220,6 +224,9 @@ void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_inte
     launch_residual_fine_zm<T, T>(x, b, r, lb.d, hd->fc64, 1.0, nullptr, hd->stream);
   else if (l == 0)
     launch_residual_fine<T, T>(x, b, r, lb.d, hd->fc64, 1.0, zero_interior, nullptr, hd->stream);
+  else if (sizeof(T) == 8 && !zero_interior && lb.d.nx % 2 == 0 && aligned16(x) && aligned16(b) &&
+           aligned16(r))  // FP64: 56 against 88 us at 128^3; FP32 is faster one node per thread
+    launch_residual_pair_gen<T>(x, b, r, lb.d, Prec<T>::S(lb), hd->stream);
   else
     launch_residual_gen<T>(x, b, r, lb.d, Prec<T>::S(lb), zero_interior, nullptr, hd->stream);
 }
@@ -618,10 +625,6 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   inf->cycles = cycles;
   return finish(launch_check());
 }
-
-// Kernels that move column pairs as one two-wide access need 16-byte aligned
-// node vectors (every device allocation is; an offset view may not be).
-static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol, int max_cycles,
                       qs_solve_info* info) {

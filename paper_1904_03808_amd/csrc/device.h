@@ -62,6 +62,10 @@ template <typename T>
 void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
                             hipStream_t s);
 bool colour_pair_supported(Dims d);
+// Coarse residual r = b - A x on the interior, two nodes per thread (even nx,
+// 16-byte aligned vectors).
+template <typename T>
+void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* S, hipStream_t s);
 
 // Fine-level row-parity half sweep (kernels_sweep.hip): updates every node
 // of the rows with parity row_par, reading own rows from own_src, neighbour

@@ -430,6 +430,79 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
   }
 }
 
+// Coarse residual r = b - A x (V-cycle form: no norm) for the column pair
+// (2p, 2p+1) of one row and plane per thread.  The four-column window of each
+// neighbour row serves both nodes, so a launch issues half the neighbour
+// loads of one thread per node; each node's terms are summed in the order of
+// k_residual_gen, so the two kernels give the same values.
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__ x,
+                                                           const T* __restrict__ b,
+                                                           T* __restrict__ r, int nx, int ny,
+                                                           int nz, const T* __restrict__ S) {
+  using V = typename Pair<T>::type;
+  __shared__ T sc[243];
+  const int W = nx / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = 1 + static_cast<int>(blockIdx.y);
+  const bool active = t < W * ny;
+  for (int e = threadIdx.x; e < 243; e += blockDim.x) sc[e] = S[static_cast<size_t>(k) * 243 + e];
+  const int tt = active ? t : 0;
+  const int p = tt % W, j = tt / W;
+  const int i0 = 2 * p;
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int il = i0 == 0 ? nx - 1 : i0 - 1;  // column i0-1
+  const int ir = i0 + 2 == nx ? 0 : i0 + 2;  // column i0+2
+  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
+  const int o = k * P + j * nx + i0;
+  T acc0[3], acc1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const V bv = *reinterpret_cast<const V*>(b + c * C + o);
+    acc0[c] = bv.x;
+    acc1[c] = bv.y;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int oz = 0; oz < 3; ++oz) {
+    const int kk = k + oz - 1;
+    T w[3][4][3];  // rows j-1, j, j+1; columns i0-1 .. i0+2
+#pragma unroll
+    for (int y = 0; y < 3; ++y) {
+      const int row = kk * P + ys[y] * nx;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const V v = *reinterpret_cast<const V*>(x + c * C + row + i0);
+        w[y][1][c] = v.x;
+        w[y][2][c] = v.y;
+        w[y][0][c] = x[c * C + row + il];
+        w[y][3][c] = x[c * C + row + ir];
+      }
+    }
+#pragma unroll
+    for (int y = 0; y < 3; ++y) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const T* B = sc + (oz * 9 + y * 3 + q) * 9;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc0[c] -= B[c * 3] * w[y][q][0] + B[c * 3 + 1] * w[y][q][1] + B[c * 3 + 2] * w[y][q][2];
+          acc1[c] -= B[c * 3] * w[y][q + 1][0] + B[c * 3 + 1] * w[y][q + 1][1] +
+                     B[c * 3 + 2] * w[y][q + 1][2];
+        }
+      }
+    }
+  }
+  if (!active) return;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    V v;
+    v.x = acc0[c];
+    v.y = acc1[c];
+    *reinterpret_cast<V*>(r + c * C + o) = v;
+  }
+}
+
 // b_c(I) = sum over the 27 fine nodes around 2I of w * r(f), w = prod (1 or 1/2).
 // One thread per coarse node; per fine row it loads the pair (2I, 2I+1) as one
 // two-wide access and takes 2I-1 from the lane to its left (a separate load
@@ -645,6 +718,13 @@ void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, co
                        cr, rpb, S, Dinv);
 }
 
+template <typename T>
+void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* S, hipStream_t s) {
+  const dim3 grid(blocks_for(static_cast<long long>(d.nx / 2) * d.ny, 256), d.nz - 1);
+  if (d.nz - 1 <= 0) return;
+  hipLaunchKernelGGL(k_residual_pair_gen<T>, grid, dim3(256), 0, s, x, b, r, d.nx, d.ny, d.nz, S);
+}
+
 int residual_blocks(Dims d) {
   const int flat = blocks_for(static_cast<long long>(d.nx) * d.ny * (d.nz - 1), kReduceBlock);
   const int planes = blocks_for(static_cast<long long>(d.nx) * d.ny, kReduceBlock) * (d.nz - 1);
@@ -742,6 +822,7 @@ void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, do
   template void launch_colour_gen<T>(T*, const T*, Dims, int, const T*, const T*, hipStream_t);  \
   template void launch_colour_pair_gen<T>(T*, const T*, Dims, int, const T*, const T*,           \
                                           hipStream_t);                                          \
+  template void launch_residual_pair_gen<T>(const T*, const T*, T*, Dims, const T*, hipStream_t); \
   template int launch_residual_gen<T>(const T*, const T*, T*, Dims, const T*, bool, double*,     \
                                       hipStream_t);                                              \
   template void launch_restrict<T>(const T*, T*, T*, Dims, hipStream_t);                         \
