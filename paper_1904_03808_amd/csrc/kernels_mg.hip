@@ -99,11 +99,59 @@ __global__ __launch_bounds__(256) void k_colour_fine(T* __restrict__ x, const T*
 // Plane k's 243 stencil entries followed by its 9 inverse-centre entries,
 // copied into LDS by every thread of the block (one load each, issued before
 // the neighbour loads so that waiting for them does not wait for those).
+// Blocks of 64 threads take four entries each: all loads are issued before
+// the first store, so a thread waits for one round of memory latency.
 template <typename T>
 __device__ __forceinline__ void stage_stencil_inverse(T* sc, const T* __restrict__ S,
                                                       const T* __restrict__ Dinv, int k) {
-  for (int e = threadIdx.x; e < 252; e += blockDim.x)
-    sc[e] = e < 243 ? S[static_cast<size_t>(k) * 243 + e] : Dinv[static_cast<size_t>(k) * 9 + e - 243];
+  T v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
+    v[u] = e < 243 ? S[static_cast<size_t>(k) * 243 + e]
+                   : (e < 252 ? Dinv[static_cast<size_t>(k) * 9 + e - 243] : T(0));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
+    if (e < 252) sc[e] = v[u];
+  }
+}
+
+// The same entries with each row (oz, y) of 27 padded to 28, so that a row
+// starts on a 16-byte boundary: S[k][oz][y][q][c][d] -> sc[(3 oz + y) 28 +
+// 9 q + 3 c + d], D^-1 at sc[252].
+template <typename T>
+__device__ __forceinline__ void stage_stencil_inverse_rows(T* sc, const T* __restrict__ S,
+                                                           const T* __restrict__ Dinv, int k) {
+  T v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
+    v[u] = e < 243 ? S[static_cast<size_t>(k) * 243 + e]
+                   : (e < 252 ? Dinv[static_cast<size_t>(k) * 9 + e - 243] : T(0));
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
+    if (e < 243)
+      sc[(e / 27) * 28 + e % 27] = v[u];
+    else if (e < 252)
+      sc[9 * 28 + e - 243] = v[u];
+  }
+}
+
+// One padded row of 28 entries from LDS in 16-byte reads.
+template <typename T>
+__device__ __forceinline__ void lds_row28(const T* p, T out[28]) {
+  constexpr int per = 16 / static_cast<int>(sizeof(T));
+  typedef T Vn __attribute__((ext_vector_type(16 / sizeof(T))));
+#pragma unroll
+  for (int u = 0; u < 28 / per; ++u) {
+    const Vn v = *reinterpret_cast<const Vn*>(p + u * per);
+#pragma unroll
+    for (int i = 0; i < per; ++i) out[u * per + i] = v[i];
+  }
 }
 
 template <typename T>
@@ -326,7 +374,7 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
                                                          const T* __restrict__ S,
                                                          const T* __restrict__ Dinv) {
   using V = typename Pair<T>::type;
-  __shared__ T sc[252];
+  __shared__ __align__(16) T sc[9 * 28 + 9];  // 9 rows (oz, y) of 27 entries, padded; D^-1
   __shared__ T xa[3][256];
   const int W = nx / 2;  // column pairs per row
   const int tid = threadIdx.x;
@@ -334,7 +382,7 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
   const int jj = blockIdx.x * rows_per_block + rr;
   const bool active = rr < rows_per_block && jj < cr.hy;
   const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
-  stage_stencil_inverse<T>(sc, S, Dinv, k);
+  stage_stencil_inverse_rows<T>(sc, S, Dinv, k);
   constexpr int xf = XF;  // x parity of the colour updated first (cr.a)
   const int j = 2 * (active ? jj : 0) + cr.bb;
   const int i0 = 2 * p;
@@ -377,9 +425,14 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
     }
 #pragma unroll
     for (int y = 0; y < 3; ++y) {
+      // the row's three blocks (27 entries, padded to 28) come from LDS in
+      // 16-byte reads issued together, so a thread waits for LDS about once
+      // per row (small levels run one wavefront per SIMD, which hides nothing)
+      T cb[28];
+      lds_row28<T>(sc + (oz * 3 + y) * 28, cb);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const T* B = sc + (oz * 9 + y * 3 + q) * 9;
+        const T* B = cb + q * 9;
         if (oz == 1 && y == 1) {
           if (q == 1) continue;  // centre blocks
         } else {
@@ -395,7 +448,7 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
       }
     }
   }
-  const T* Di = sc + 243;
+  const T* Di = sc + 9 * 28;
   T na[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) na[c] = Di[c * 3] * acca[0] + Di[c * 3 + 1] * acca[1] + Di[c * 3 + 2] * acca[2];
@@ -412,8 +465,8 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
     side[1 - xf][c] = xa[c][tn];
   }
   {
-    const T* Bl = sc + (9 + 3 + 0) * 9;  // oz = 1, y = 1, q = 0: x - 1
-    const T* Br = sc + (9 + 3 + 2) * 9;  // q = 2: x + 1
+    const T* Bl = sc + (3 + 1) * 28 + 0 * 9;  // oz = 1, y = 1, q = 0: x - 1
+    const T* Br = sc + (3 + 1) * 28 + 2 * 9;  // q = 2: x + 1
 #pragma unroll
     for (int c = 0; c < 3; ++c)
       accb[c] -= Bl[c * 3] * side[0][0] + Bl[c * 3 + 1] * side[0][1] + Bl[c * 3 + 2] * side[0][2] +
@@ -505,8 +558,7 @@ __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__
 
 // b_c(I) = sum over the 27 fine nodes around 2I of w * r(f), w = prod (1 or 1/2).
 // One thread per coarse node; per fine row it loads the pair (2I, 2I+1) as one
-// two-wide access and takes 2I-1 from the lane to its left (a separate load
-// only on the first lane of a wave or of a row).
+// two-wide access and 2I-1 on its own.
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __restrict__ bc,
                                                   T* __restrict__ xc, int nxf, int nyf, int nzf) {
@@ -515,34 +567,39 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = nxc * nyc * (nzc - 1);
   if (total <= 0) return;
-  const bool act = t < total;
-  const int tt = act ? t : total - 1;  // lanes past the end still take part in the shuffles
-  const int I = tt % nxc, J = (tt / nxc) % nyc, K = 1 + tt / (nxc * nyc);
-  const bool own_left = (threadIdx.x & 63) == 0 || I == 0;
+  if (t >= total) return;
+  const int I = t % nxc, J = (t / nxc) % nyc, K = 1 + t / (nxc * nyc);
   const int il = I == 0 ? nxf - 1 : 2 * I - 1;
   const int Pf = nxf * nyf, Cf = (nzf + 1) * Pf;
   const int Pc = nxc * nyc, Cc = (nzc + 1) * Pc;
   const int ys[3] = {wrap_m(2 * J, nyf), 2 * J, 2 * J + 1};
   const T w[3] = {T(0.5), T(1), T(0.5)};
+  // the 54 loads of a component are all issued before any value is used, so
+  // the thread waits for one round of memory latency per component
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    V v[3][3];
+    T left[3][3];
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const T* row = r + c * Cf + (2 * K + dz - 1) * Pf + ys[dy] * nxf;
+        v[dz][dy] = *reinterpret_cast<const V*>(row + 2 * I);
+        left[dz][dy] = row[il];
+      }
     T acc = T(0);
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz) {
-      const int kf = 2 * K + dz - 1;
       T az = T(0);
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
-        const T* row = r + c * Cf + kf * Pf + ys[dy] * nxf;
-        const V v = *reinterpret_cast<const V*>(row + 2 * I);
-        T left = __shfl_up(v.y, 1, 64);
-        if (own_left) left = row[il];
-        const T ax = T(0.5) * left + v.x + T(0.5) * v.y;
+        const T ax = T(0.5) * left[dz][dy] + v[dz][dy].x + T(0.5) * v[dz][dy].y;
         az += w[dy] * ax;
       }
       acc += w[dz] * az;
     }
-    if (act) {
+    {
       bc[c * Cc + K * Pc + J * nxc + I] = acc;
       if (xc) xc[c * Cc + K * Pc + J * nxc + I] = T(0);
     }
@@ -576,19 +633,27 @@ __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T*
   const bool oy = j & 1;
   const T wy = oy ? T(0.5) : T(1), wz = T(0.5);
   // x-y combination of coarse plane K for the even and the odd fine column
+  // (the row j1 is loaded on even fine rows too, where it is j0, so that all
+  // twelve loads are issued before any is used)
   auto coarse = [&](int K, T pe[3], T po[3]) {
+    T a0[3], a1[3], b0[3], b1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const T* p0 = ec + c * Cc + K * Pc + j0 * nxc;
-      const T a0 = p0[i0], a1 = p0[i1];
+      const T* p1 = ec + c * Cc + K * Pc + j1 * nxc;
+      a0[c] = p0[i0];
+      a1[c] = p0[i1];
+      b0[c] = p1[i0];
+      b1[c] = p1[i1];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
       if (oy) {
-        const T* p1 = ec + c * Cc + K * Pc + j1 * nxc;
-        const T b0 = p1[i0], b1 = p1[i1];
-        pe[c] = wy * (a0 + b0);
-        po[c] = wy * (T(0.5) * (a0 + a1) + T(0.5) * (b0 + b1));
+        pe[c] = wy * (a0[c] + b0[c]);
+        po[c] = wy * (T(0.5) * (a0[c] + a1[c]) + T(0.5) * (b0[c] + b1[c]));
       } else {
-        pe[c] = a0;
-        po[c] = T(0.5) * (a0 + a1);
+        pe[c] = a0[c];
+        po[c] = T(0.5) * (a0[c] + a1[c]);
       }
     }
   };
