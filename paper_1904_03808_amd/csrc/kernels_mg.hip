@@ -120,7 +120,7 @@ __device__ __forceinline__ void stage_stencil_inverse(T* sc, const T* __restrict
 
 // The same entries with each row (oz, y) of 27 padded to 28, so that a row
 // starts on a 16-byte boundary: S[k][oz][y][q][c][d] -> sc[(3 oz + y) 28 +
-// 9 q + 3 c + d], D^-1 at sc[252].
+// 9 q + 3 c + d], D^-1 at sc[252] (when Dinv is given).
 template <typename T>
 __device__ __forceinline__ void stage_stencil_inverse_rows(T* sc, const T* __restrict__ S,
                                                            const T* __restrict__ Dinv, int k) {
@@ -129,14 +129,14 @@ __device__ __forceinline__ void stage_stencil_inverse_rows(T* sc, const T* __res
   for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
     v[u] = e < 243 ? S[static_cast<size_t>(k) * 243 + e]
-                   : (e < 252 ? Dinv[static_cast<size_t>(k) * 9 + e - 243] : T(0));
+                   : (e < 252 && Dinv ? Dinv[static_cast<size_t>(k) * 9 + e - 243] : T(0));
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
     if (e < 243)
       sc[(e / 27) * 28 + e % 27] = v[u];
-    else if (e < 252)
+    else if (e < 252 && Dinv)
       sc[9 * 28 + e - 243] = v[u];
   }
 }
@@ -297,11 +297,11 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restri
   // neighbour planes are visited in a loop that is not unrolled: each visit
   // issues its 27 loads together, so a thread waits for three rounds of memory
   // latency and holds one plane's neighbours in registers.
-  __shared__ T sc[243];
+  __shared__ __align__(16) T sc[9 * 28];  // rows (oz, y) padded to 28
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 1 + static_cast<int>(blockIdx.y);
   const bool active = t < nx * ny;
-  for (int e = threadIdx.x; e < 243; e += blockDim.x) sc[e] = S[static_cast<size_t>(k) * 243 + e];
+  stage_stencil_inverse_rows<T>(sc, S, nullptr, k);
   const int tt = active ? t : 0;
   const int P = nx * ny, C = (nz + 1) * P;
   const int i = tt % nx, j = tt / nx;
@@ -324,11 +324,17 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restri
       for (int c = 0; c < 3; ++c) nb[q][c] = x[c * C + off];
     }
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const T* B = sc + (oz * 9 + q) * 9;
+    for (int y = 0; y < 3; ++y) {
+      T cb[28];
+      lds_row28<T>(sc + (oz * 3 + y) * 28, cb);
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        acc[c] -= B[c * 3] * nb[q][0] + B[c * 3 + 1] * nb[q][1] + B[c * 3 + 2] * nb[q][2];
+      for (int x3 = 0; x3 < 3; ++x3) {
+        const int q = y * 3 + x3;
+        const T* B = cb + x3 * 9;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          acc[c] -= B[c * 3] * nb[q][0] + B[c * 3 + 1] * nb[q][1] + B[c * 3 + 2] * nb[q][2];
+      }
     }
   }
   double sq = 0.0;
@@ -494,12 +500,12 @@ __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__
                                                            T* __restrict__ r, int nx, int ny,
                                                            int nz, const T* __restrict__ S) {
   using V = typename Pair<T>::type;
-  __shared__ T sc[243];
+  __shared__ __align__(16) T sc[9 * 28];  // rows (oz, y) padded to 28
   const int W = nx / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 1 + static_cast<int>(blockIdx.y);
   const bool active = t < W * ny;
-  for (int e = threadIdx.x; e < 243; e += blockDim.x) sc[e] = S[static_cast<size_t>(k) * 243 + e];
+  stage_stencil_inverse_rows<T>(sc, S, nullptr, k);
   const int tt = active ? t : 0;
   const int p = tt % W, j = tt / W;
   const int i0 = 2 * p;
@@ -534,9 +540,11 @@ __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__
     }
 #pragma unroll
     for (int y = 0; y < 3; ++y) {
+      T cb[28];
+      lds_row28<T>(sc + (oz * 3 + y) * 28, cb);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const T* B = sc + (oz * 9 + y * 3 + q) * 9;
+        const T* B = cb + q * 9;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           acc0[c] -= B[c * 3] * w[y][q][0] + B[c * 3 + 1] * w[y][q][1] + B[c * 3 + 2] * w[y][q][2];
