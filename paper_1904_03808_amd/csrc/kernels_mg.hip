@@ -780,7 +780,9 @@ void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, co
   const ColourRange cr = colour_range(d, colour);
   if (cr.total() <= 0) return;
   const int W = d.nx / 2;
-  const int rpb = std::max(1, std::min(cr.hy, 256 / W));
+  // whole rows in workgroups of about 128 threads: more, smaller workgroups
+  // than 256-thread ones (measured: 5.3 against 6.3 us at 64^3, same at 128^3)
+  const int rpb = std::max(1, std::min(cr.hy, 128 / W));
   const int threads = (rpb * W + 63) / 64 * 64;
   const dim3 grid(blocks_for(cr.hy, rpb), cr.nk);
   if (cr.a)
