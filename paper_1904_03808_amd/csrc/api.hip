@@ -90,7 +90,8 @@ struct qs_handle {
   double* partial = nullptr;
   int partial_n = 0;
   double* dnorm = nullptr;   // device, 4 doubles
-  double* pinned = nullptr;  // host pinned, 4 doubles
+  double* pinned = nullptr;      // host pinned, 4 doubles
+  double* pinned_dev = nullptr;  // the same memory as the device addresses it (null: copy instead)
   bool row_sweep = false;    // colour order allows the row-parity sweep kernel
   size_t lds_limit = 0;      // bytes of LDS a workgroup may use
 };
@@ -169,12 +170,19 @@ qs_status launch_check() {
   return e == hipSuccess ? QS_OK : hip_fail("kernel launch", e);
 }
 
-// Read the reduced double written to hd->dnorm[0].
+// Read the reduced double written to hd->dnorm[0] (and, when the pinned
+// buffer is device-addressable, by the reduction kernel straight into it).
+// The host polls the stream rather than sleeping in a synchronisation, so the
+// next cycle is enqueued as soon as the norm is there.
 qs_status read_norm(qs_handle* hd, double* out) {
   QS_HIP(hipGetLastError());
-  QS_HIP(hipMemcpyAsync(hd->pinned, hd->dnorm, sizeof(double), hipMemcpyDeviceToHost, hd->stream));
-  QS_HIP(hipStreamSynchronize(hd->stream));
-  *out = hd->pinned[0];
+  if (!hd->pinned_dev)
+    QS_HIP(hipMemcpyAsync(hd->pinned, hd->dnorm, sizeof(double), hipMemcpyDeviceToHost, hd->stream));
+  hipError_t q;
+  while ((q = hipStreamQuery(hd->stream)) == hipErrorNotReady) {
+  }
+  QS_HIP(q);
+  *out = static_cast<volatile double*>(hd->pinned)[0];
   return QS_OK;
 }
 
@@ -358,7 +366,7 @@ int residual_norm0(qs_handle* hd, const double* x, const double* b, Tout* r, dou
                                                hd->partial, hd->stream)
           : launch_residual_fine_zm<double, Tout>(x, b, r, hd->L[0].d, hd->fc64, scale,
                                                   hd->partial, hd->stream);
-  launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->stream);
+  launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->pinned_dev, hd->stream);
   return nb;
 }
 
@@ -431,6 +439,11 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
       delete hd;
       return hip_fail("hipHostMalloc", e);
     }
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, hd->pinned, 0) == hipSuccess && dp)
+      hd->pinned_dev = static_cast<double*>(dp);
+    else
+      (void)hipGetLastError();  // fall back to a copy per norm
   }
   const double lam = p->lambda, mu = p->mu, h = p->h;
   {
@@ -582,7 +595,7 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
         double* xn = xs == x ? l0.xalt64 : x;
         const int nb = launch_update_residual_zm(xs, l0.x32, e_scale, xn, b, l0.b32, d0, hd->fc64,
                                                  1.0 / scale_used, hd->partial, hd->stream);
-        launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->stream);
+        launch_reduce_sum(hd->partial, nb, hd->dnorm, hd->pinned_dev, hd->stream);
         xs = xn;
         pending = false;
       } else {

@@ -121,7 +121,10 @@ template <typename T>
 void launch_prolong_add(T* x, const T* ec, Dims fine, hipStream_t s);
 
 // Deterministic sum of partial[0..n) into out[0].
-void launch_reduce_sum(const double* partial, int n, double* out, hipStream_t s);
+// Sum of n partials in a fixed order into out[0] (device) and, if given,
+// out_host[0] (device address of pinned host memory).
+void launch_reduce_sum(const double* partial, int n, double* out, double* out_host,
+                       hipStream_t s);
 
 template <typename T>
 void launch_fill(T* x, size_t n, T value, hipStream_t s);

@@ -694,7 +694,8 @@ __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T*
 }
 
 __global__ __launch_bounds__(1024) void k_reduce_sum(const double* __restrict__ partial, int n,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out,
+                                                     double* __restrict__ out_host) {
   __shared__ double red[16];
   double s = 0.0;
   for (int q = threadIdx.x; q < n; q += blockDim.x) s += partial[q];
@@ -707,6 +708,7 @@ __global__ __launch_bounds__(1024) void k_reduce_sum(const double* __restrict__ 
     double t = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
     out[0] = t;
+    if (out_host) out_host[0] = t;
   }
 }
 
@@ -743,8 +745,20 @@ __global__ __launch_bounds__(256) void k_dense_matvec(const double* __restrict__
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const double* a = A + static_cast<size_t>(row) * n;
-  double s = 0.0;
-  for (int q = lane; q < n; q += 64) s += a[q] * v[q];
+  // four independent partial sums, so that each step issues eight loads
+  // before it waits
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int q = lane;
+  for (; q + 192 < n; q += 256) {
+    const double a0 = a[q], a1 = a[q + 64], a2 = a[q + 128], a3 = a[q + 192];
+    const double v0 = v[q], v1 = v[q + 64], v2 = v[q + 128], v3 = v[q + 192];
+    s0 += a0 * v0;
+    s1 += a1 * v1;
+    s2 += a2 * v2;
+    s3 += a3 * v3;
+  }
+  for (; q < n; q += 64) s0 += a[q] * v[q];
+  double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) out[row] = s;
@@ -864,8 +878,9 @@ void launch_prolong_add(T* x, const T* ec, Dims f, hipStream_t s) {
                      f.ny, f.nz, kseg);
 }
 
-void launch_reduce_sum(const double* partial, int n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(1024), 0, s, partial, n, out);
+void launch_reduce_sum(const double* partial, int n, double* out, double* out_host,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(1024), 0, s, partial, n, out, out_host);
 }
 
 template <typename T>
