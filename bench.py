@@ -227,6 +227,25 @@ def config4_adjoint(n: int = 96, steps: int = 10) -> dict:
             "loss": loss.item(), "solver": "fp64, rtol 1e-10 forward and transposed"}
 
 
+def profile_solve(n: int) -> None:
+    """Kernels for hardware-counter runs of a whole V-cycle: two FP32-IR cycles
+    (fixed count, no convergence test) of the n^3 bench system."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, stress_field
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp32-ir", device=dev)
+    sig = torch.from_numpy(stress_field(n, n, n, 2)).to(dev)
+    b = g.rhs(sig, 1.0)
+    del sig
+    x = torch.zeros_like(b)
+    g.solve(b, x, rtol=0.0, max_cycles=2, raise_on_failure=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": "fp32-ir solve", "cycles": 2}), flush=True)
+
+
 def profile_smoother(n: int) -> None:
     """Kernels for hardware-counter runs: one device-to-device copy of a known
     size (calibrates FETCH_SIZE / WRITE_SIZE), then 3 fine-level sweeps in FP32
@@ -265,6 +284,8 @@ def main():
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 comparison block")
     ap.add_argument("--no-steps", action="store_true",
                     help="skip the shear-step (256^3) and adjoint (96^3) blocks")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="only run two FP32-IR V-cycles (for rocprofv3 counters)")
     ap.add_argument("--profile-smoother", action="store_true",
                     help="only run a calibration copy and fine-level sweeps (for rocprofv3 counters)")
     args = ap.parse_args()
@@ -281,6 +302,9 @@ def main():
 
     if args.profile_smoother:
         profile_smoother(args.n)
+        return
+    if args.profile_solve:
+        profile_solve(args.n)
         return
     n = args.n
     h = 1.0 / n
