@@ -28,13 +28,14 @@
  * no device memory: its hierarchy lives in a caller-provided device
  * workspace of qs_workspace_bytes() bytes that must stay valid until
  * qs_destroy().  The handle itself (host memory, plus a few bytes of pinned
- * host memory for reading back norms) is owned by the library.
+ * host memory into which the device writes the residual norms) is owned by
+ * the library.
  *
  * Streams.  All work is enqueued on the stream given to qs_setup() (a
  * hipStream_t passed as void*; NULL = default stream).  Entry points that
- * return host-visible results (qs_mg_solve, qs_projection_step) synchronise
- * that stream once per V-cycle to read the residual norm; the others are
- * asynchronous.  Calls on one handle must not overlap.
+ * return host-visible results (qs_mg_solve, qs_projection_step) wait for that
+ * stream once per V-cycle (the calling thread polls it) to read the residual
+ * norm; the others are asynchronous.  Calls on one handle must not overlap.
  *
  * Errors.  Every entry point returns a qs_status; nothing is thrown and the
  * process is never aborted.  On QS_ERR_HIP the stream may hold partial work.
