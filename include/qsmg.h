@@ -69,7 +69,10 @@ typedef enum { QS_FP64 = 0, QS_FP32_IR = 1 } qs_precision;
 /* Multigrid parameters (Sec. 3.6).  Coarsening halves every dimension while
  * nz > min_coarse_nz; each coarsened level needs even nx, ny, nz and at least
  * 4 cells per dimension; the coarsest level is solved with a dense FP64
- * inverse (at most QS_MAX_COARSE unknowns).  colour_order lists the 8 node
+ * inverse (at most QS_MAX_COARSE unknowns).  Kernels index arrays with 32-bit
+ * integers, so 3 (nz+1) ny nx (node vector) and 6 nz ny nx (cell tensor)
+ * must stay below 2^31 (512^3 passes, 640 x 640 x 1024 does not); larger
+ * grids are refused with QS_ERR_SHAPE.  colour_order lists the 8 node
  * colours c = (i&1) + 2*(j&1) + 4*(k&1) in the order pre-smoothing visits
  * them; post-smoothing visits them in reverse. */
 #define QS_MAX_COARSE 6144

@@ -68,9 +68,12 @@ bool valid_params(const qs_params* p) {
 
 int plan(const qs_params* p, std::vector<int>* dims) {
   if (plan_levels(p->nx, p->ny, p->nz, p->min_coarse_nz, dims) != 0) return -2;
-  // 32-bit element indexing inside the kernels
-  const long long elems = 3LL * (p->nz + 1) * p->ny * p->nx;
-  if (elems >= (1LL << 31) || static_cast<int>(dims->size() / 3) > kMaxLevels) return -2;
+  // 32-bit element indexing inside the kernels: node vectors and cell tensors
+  const long long nodes = 3LL * (p->nz + 1) * p->ny * p->nx;
+  const long long cells = 6LL * p->nz * p->ny * p->nx;
+  if (nodes >= (1LL << 31) || cells >= (1LL << 31) ||
+      static_cast<int>(dims->size() / 3) > kMaxLevels)
+    return -2;
   return 0;
 }
 

@@ -115,6 +115,10 @@ def test_workspace_sizing_and_argument_errors(lib):
     assert lib.qs_workspace_bytes(C.byref(params(33, 32, 32)), C.byref(bad)) == _capi.QS_ERR_SHAPE
     assert lib.qs_workspace_bytes(C.byref(params(64, 64, 16, min_coarse_nz=16)),
                                   C.byref(bad)) == _capi.QS_ERR_SHAPE
+    # 32-bit indexing: a coarsenable grid whose cell tensor has 6 nz ny nx >= 2^31
+    # elements is refused, 512^3 is not
+    assert lib.qs_workspace_bytes(C.byref(params(640, 640, 1024)), C.byref(bad)) == _capi.QS_ERR_SHAPE
+    assert lib.qs_workspace_bytes(C.byref(params(512, 512, 512)), C.byref(bad)) == _capi.QS_OK
     # null handles are refused before anything touches a device
     assert lib.qs_destroy(None) == _capi.QS_ERR_ARG
     assert lib.qs_mg_solve(None, None, None, C.c_double(1e-10), 10, None) == _capi.QS_ERR_ARG
