@@ -94,10 +94,30 @@ def cpu_baseline(n_full: int, cycles_full: int) -> dict:
             "host_cpus": os.cpu_count()}
 
 
-def solve_pair(n: int, b, steps: int, warmup: int) -> dict:
+def smoother_timing(g, b, dtype, bytes_per_node: float) -> dict:
+    """Fine-level full sweeps of solver g on its own: HIP events on the
+    library's stream; the difference of a 5-sweep and a 1-sweep call leaves 4
+    sweeps of the kernel alone (one call also moves the wall planes of the
+    ping-pong buffer).  One sweep = two row-parity half sweeps (k_sweep_rows),
+    each updating half of the nodes."""
+    import torch
+    n3 = g.node_shape(0)
+    nodes = n3[3] * n3[2] * (n3[1] - 2)
+    xs = torch.zeros(n3, dtype=dtype, device=b.device)
+    bs = b.to(dtype)
+    g.smooth(0, xs, bs, 1)
+    t5 = _events_ms(lambda: g.smooth(0, xs, bs, 5), 5)
+    t1 = _events_ms(lambda: g.smooth(0, xs, bs, 1), 5)
+    ms = (t5 - t1) / 4
+    del xs, bs
+    return {"ms_per_sweep": ms, "launches_per_sweep": 2, "avg_launch_us": ms * 1e3 / 2,
+            "effective_GBs": bytes_per_node * nodes / (ms * 1e-3) / 1e9}
+
+
+def solve_pair(n: int, b, steps: int, warmup: int, smoother: bool = False) -> dict:
     """FP32-IR and FP64 solves of K x = b from x = 0 to 1e-10 at n^3; wall time
     per solve between device synchronisations, and the two solutions' relative
-    L2 difference."""
+    L2 difference (with `smoother`, also the fine-level sweep timing)."""
     import torch
 
     from paper_1904_03808_amd.qsmg import MGSolver
@@ -120,6 +140,10 @@ def solve_pair(n: int, b, steps: int, warmup: int) -> dict:
         out[name] = {"ms_per_solve": dt * 1e3, "solves_per_s": 1.0 / dt, "cycles": info.cycles,
                      "rel_res": info.rel_res, "levels": g.levels,
                      "ms_per_cycle": dt * 1e3 / max(info.cycles, 1)}
+        if smoother:
+            fp32 = prec == "fp32-ir"
+            out[name]["smoother"] = smoother_timing(g, b, torch.float32 if fp32 else torch.float64,
+                                                    36.0 if fp32 else 72.0)
         sols[name] = x
         g.close()
     out["fp32ir_vs_fp64_rel_l2"] = (torch.linalg.vector_norm(sols["fp32_ir"] - sols["fp64"])
@@ -144,7 +168,7 @@ def config_512(steps: int = 3, warmup: int = 1) -> dict:
     b = g.rhs(sig, 1.0)
     del sig
     g.close()
-    out = solve_pair(n, b, steps, warmup)
+    out = solve_pair(n, b, steps, warmup, smoother=True)
     out["grid"] = [n, n, n]
     out["steps"] = steps
     out["rhs"] = "D_h sigma, sigma smoothed N(0,1) generated on the device (seed 2)"
@@ -341,22 +365,8 @@ def main():
     del results["fp32_ir_x"], results["fp64_x"]
 
     # smoother on its own: fine level, full sweeps, HIP events on the same stream
-    sm = {}
-    for name, g, dt_, bpn in (("fp32", g32, torch.float32, 36.0), ("fp64", g64, torch.float64, 72.0)):
-        xs = torch.zeros(g.node_shape(0), dtype=dt_, device=dev)
-        bs = b.to(dt_)
-        g.smooth(0, xs, bs, 1)
-        # one call also moves the wall planes of the ping-pong buffer; the
-        # difference of a 5-sweep and a 1-sweep call leaves 4 sweeps of the
-        # kernel alone.  One sweep = two row-parity half sweeps (k_sweep_rows),
-        # each updating half of the nodes.
-        t5 = _events_ms(lambda: g.smooth(0, xs, bs, 5), 5)
-        t1 = _events_ms(lambda: g.smooth(0, xs, bs, 1), 5)
-        ms = (t5 - t1) / 4
-        sm[name] = {"ms_per_sweep": ms, "launches_per_sweep": 2,
-                    "avg_launch_us": ms * 1e3 / 2,
-                    "effective_GBs": bpn * nodes / (ms * 1e-3) / 1e9}
-        del xs, bs
+    sm = {"fp32": smoother_timing(g32, b, torch.float32, 36.0),
+          "fp64": smoother_timing(g64, b, torch.float64, 72.0)}
     # roofline kernel: one FP32 half sweep; algorithmic bytes per launch =
     # 36 B x (interior nodes / 2), over the average launch time from HIP events
     algo_bytes = 36.0 * nodes / 2
