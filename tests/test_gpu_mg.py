@@ -209,12 +209,14 @@ def test_fp32_refinement(n):
 
 
 @pytest.mark.parametrize("n,mc", [((32, 32, 32), 4), ((40, 24, 32), 4), ((16, 16, 64), 16),
-                                  ((256, 16, 16), 4), ((512, 16, 16), 4), ((128, 10, 8), 4)])
+                                  ((256, 16, 16), 4), ((512, 16, 16), 4), ((128, 10, 8), 4),
+                                  ((8, 8, 16), 8)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
 def test_row_sweep_matches_oracle(n, mc, prec):
     """The row-parity sweep kernel (ping-pong, z-segments, halo recomputation,
     row lengths with and without a specialised kernel, last row groups that
-    repeat a row: 16 x 16 and 128 x 10) equals the oracle's colour-by-colour
+    repeat a row: 16 x 16, 128 x 10, and 8 x 8, where one group of 64 rows
+    holds the 4 rows of a parity) equals the oracle's colour-by-colour
     Gauss-Seidel sweep on every smoothed level, for 1 and 3 sweeps."""
     rng = np.random.default_rng(10)
     g, o = make(*n, precision=prec, min_coarse_nz=mc)
