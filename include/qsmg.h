@@ -91,7 +91,9 @@ typedef struct {
   int cycles;                      /* V-cycles performed                     */
   int levels;                      /* multigrid levels                       */
   double rel_res;                  /* final ||b_eff - K x|| / ||b_eff||      */
-  double rel_res_hist[QS_HIST];    /* before cycle 0, after cycle 1, ...     */
+  double rel_res_hist[QS_HIST];    /* before cycle 0, after cycle 1, ...;
+                                      NaN after a V-cycle with no residual
+                                      check (FP32_IR, see qs_mg_solve)       */
 } qs_solve_info;
 
 /* STZ constants in units of stress E, time t_s = L/c_s and chi in e_z/k_B
@@ -130,7 +132,10 @@ qs_status qs_apply(qs_handle* hd, const double* x, double* y);
 
 /* Solve K x = b for the interior of x by V-cycles (Sec. 3.6) until
  * ||b_eff - K x||_2 <= rtol ||b_eff||_2 (b_eff = b - K_IB x_B, 2-norm over
- * the 3 nx ny (nz-1) interior unknowns), checked before each cycle.
+ * the 3 nx ny (nz-1) interior unknowns), checked before each cycle (FP64) or
+ * before each refinement step (FP32_IR: the FP64 residual, scaled, is the
+ * right-hand side of up to two FP32 V-cycles, one when the last step's
+ * contraction says one more V-cycle reaches rtol; cycles counts V-cycles).
  * x: in = initial guess with the wall velocities in planes 0 and nz (never
  * written); out = solution.  Wall planes of b are ignored.  rtol <= 0 runs
  * exactly max_cycles cycles and returns QS_OK.  b_eff == 0 gives x = 0 and

@@ -589,6 +589,11 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   double scale_used = scale;
   int cycles = 0;
   double rel = 0.0;
+  // FP32-IR: each refinement step runs up to two FP32 V-cycles on the scaled
+  // residual before the next FP64 residual; one when the contraction seen in
+  // the previous step says one more V-cycle reaches rtol.
+  double rel_prev = 0.0;
+  int inner_prev = 0;
   for (;;) {
     const bool need_norm = !fixed || cycles == max_cycles;
     if (ir) {
@@ -611,6 +616,7 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
       double rn2 = 0.0;
       st = read_norm(hd, &rn2);
       if (st != QS_OK) return finish(st);
+      rel_prev = cycles > 0 ? rel : 0.0;
       rel = std::sqrt(rn2 / nb2);
       if (cycles < QS_HIST) inf->rel_res_hist[cycles] = rel;
       inf->rel_res = rel;
@@ -621,22 +627,32 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
       if (!fixed && rel <= rtol) break;
       if (ir) scale = pow2_near(std::sqrt(rn2 / nunk));
     }
-    if (cycles == max_cycles) {
+    if (cycles >= max_cycles) {
       inf->cycles = cycles;
       return finish(fixed ? QS_OK : QS_ERR_NOT_CONVERGED);
     }
     if (ir) {
       // correction e solves A e = r / scale_used in FP32; x += scale_used e
       // is made by the next residual
+      int inner = std::min(2, max_cycles - cycles);
+      if (!fixed && inner == 2 && inner_prev > 0 && rel_prev > 0.0) {
+        const double rho = std::pow(rel / rel_prev, 1.0 / inner_prev);
+        if (rel * rho <= rtol) inner = 1;
+      }
       const bool skip_fill = hd->p.n_pre >= 1 && hd->nlev > 1 && use_row_sweep<float>(hd, 0);
       if (!skip_fill) launch_fill<float>(l0.x32, l0.d.elems(), 0.0f, hd->stream);
       vcycle<float>(hd, 0, l0.x32, l0.b32, skip_fill);
+      for (int v = 1; v < inner; ++v) vcycle<float>(hd, 0, l0.x32, l0.b32);
       pending = true;
       e_scale = scale_used;
+      for (int v = 1; v < inner && cycles + v < QS_HIST; ++v)
+        inf->rel_res_hist[cycles + v] = std::nan("");  // no FP64 residual after this V-cycle
+      cycles += inner;
+      inner_prev = inner;
     } else {
       vcycle<double>(hd, 0, x, b);
+      ++cycles;
     }
-    ++cycles;
   }
   inf->cycles = cycles;
   return finish(launch_check());
