@@ -589,9 +589,10 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   double scale_used = scale;
   int cycles = 0;
   double rel = 0.0;
-  // FP32-IR: each refinement step runs up to two FP32 V-cycles on the scaled
-  // residual before the next FP64 residual; one when the contraction seen in
-  // the previous step says one more V-cycle reaches rtol.
+  // FP32-IR: each refinement step runs up to kMaxInner FP32 V-cycles on the
+  // scaled residual before the next FP64 residual, fewer when the contraction
+  // per V-cycle seen in the previous step says fewer reach rtol.
+  constexpr int kMaxInner = 4;
   double rel_prev = 0.0;
   int inner_prev = 0;
   for (;;) {
@@ -634,10 +635,13 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
     if (ir) {
       // correction e solves A e = r / scale_used in FP32; x += scale_used e
       // is made by the next residual
-      int inner = std::min(2, max_cycles - cycles);
-      if (!fixed && inner == 2 && inner_prev > 0 && rel_prev > 0.0) {
+      int inner = std::min(kMaxInner, max_cycles - cycles);
+      if (!fixed && inner_prev > 0 && rel_prev > 0.0) {
         const double rho = std::pow(rel / rel_prev, 1.0 / inner_prev);
-        if (rel * rho <= rtol) inner = 1;
+        if (rho > 0.0 && rho < 1.0) {
+          const double need = std::ceil(std::log(rtol / rel) / std::log(rho));
+          if (need < inner) inner = std::max(1, static_cast<int>(need));
+        }
       }
       const bool skip_fill = hd->p.n_pre >= 1 && hd->nlev > 1 && use_row_sweep<float>(hd, 0);
       if (!skip_fill) launch_fill<float>(l0.x32, l0.d.elems(), 0.0f, hd->stream);
