@@ -102,6 +102,9 @@ typedef struct {
 typedef struct {
   double s_y, tau0, beta, delta_over_T, c0, chi_inf;
   double dt;               /* quasi-static time step                           */
+  double l_diff;           /* diffusion length l of Eq. chi_evo (units of L);
+                              0 leaves the diffusion term out; the reverse-mode
+                              entry points require 0                          */
 } qs_stz_params;
 
 typedef struct qs_handle qs_handle;
@@ -146,7 +149,14 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol,
 /* Pointwise STZ step at every cell (Sec. 3.1; Eq. sig_star_qs):
  * L = G_h v (velocity gradient at cell centres, Eq. stag_stenc),
  * sigma* = sigma + dt (L sigma + sigma L^T - tr(L) sigma - C : (D^pl/sbar) sigma_0),
- * chi'   = chi + (dt/c0) (2 sbar D^pl / s_y) (chi_inf - chi).
+ * chi'   = chi + (dt/c0) (2 sbar D^pl / s_y) (chi_inf - chi)
+ *              + (dt/c0) l^2 div(D^pl grad chi)                (Eq. chi_evo),
+ * the last term when l_diff = l > 0: the 7-point flux form over the six faces
+ * of a cell, each face carrying the mean of D^pl in its two cells, divided by
+ * h^2; x and y wrap; below the first and above the last cell layer a ghost
+ * layer holds the linear extrapolation of sigma and chi from the two nearest
+ * layers (Sec. 3.5), with D^pl evaluated on it (0 where the extrapolated chi
+ * is not positive).  D^pl, sbar and chi are those of step n.
  * Outputs may not alias inputs. */
 qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v,
                       const double* sigma, const double* chi, double* sigma_star,

@@ -10,7 +10,13 @@ Readings where the paper is silent or inconsistent (also in the design notes):
     Truesdell rate (Sec. 2.1) and Eq. sig_star_qs;
   * D^pl = 0 when sbar <= s_Y (the factor 1 - s_Y/sbar would be negative);
   * the effective temperature takes a forward-Euler step with the state at
-    step n; the diffusion term of Eq. chi_evo is not included (l = 0);
+    step n (Eq. chi_evo_exp written for the quasi-static step);
+  * its diffusion term l^2 div(D^pl grad chi) is the 7-point flux form on
+    cells, each face carrying the mean of D^pl in its two cells; in z the
+    ghost layer of sigma and chi is the linear extrapolation of the two
+    nearest layers (Sec. 3.5), and D^pl there is evaluated on the ghost
+    values (D^pl = 0 where the extrapolated chi is not positive); x and y
+    wrap; l = 0 leaves the term out;
   * Eq. sig_star_qs has no advection term, so none is applied.
 """
 from __future__ import annotations
@@ -56,6 +62,38 @@ def plastic_rate(sbar, chi, p):
     return np.where(act, val, 0.0 * val)
 
 
+def z_ghosts(f):
+    """f [..., nz, ny, nx] extended by one cell layer below and above in z,
+    each the linear extrapolation of the two nearest layers."""
+    lo = 2.0 * f[..., :1, :, :] - f[..., 1:2, :, :]
+    hi = 2.0 * f[..., -1:, :, :] - f[..., -2:-1, :, :]
+    return np.concatenate([lo, f, hi], axis=-3)
+
+
+def flux_divergence(D, chi, h):
+    """div(D grad chi) at the cells of the z-ghosted arrays D, chi
+    [nz+2, ny, nx] (layer 0 and nz+1 are ghosts): the 7-point flux form with
+    face coefficients (D_c + D_n) / 2; x and y wrap.  Returns [nz, ny, nx]."""
+    Dc, xc = D[1:-1], chi[1:-1]
+    out = np.zeros_like(xc)
+    for axis in (1, 2):  # y, x of the interior block (periodic)
+        for s in (-1, 1):
+            Dn, xn = np.roll(Dc, s, axis=axis), np.roll(xc, s, axis=axis)
+            out = out + 0.5 * (Dc + Dn) * (xn - xc)
+    for Dn, xn in ((D[:-2], chi[:-2]), (D[2:], chi[2:])):  # z - 1, z + 1
+        out = out + 0.5 * (Dc + Dn) * (xn - xc)
+    return out / (h * h)
+
+
+def chi_diffusion(sigma, chi, h, p):
+    """div(D^pl grad chi) per cell for the state (sigma, chi) of step n."""
+    sg, cg = z_ghosts(sigma), z_ghosts(chi)
+    _, sbar = deviator(voigt_to_full(sg))
+    pos = np.real(cg) > 0.0
+    D = np.where(pos, plastic_rate(sbar, np.where(pos, cg, 1.0), p), 0.0)
+    return flux_divergence(D, cg, h)
+
+
 def stz_pointwise(L, sigma, chi, dt, lam, mu, p):
     """The cellwise part of the step: (L, sigma, chi) -> (sigma*, chi').
 
@@ -81,9 +119,15 @@ def stz_step(v, sigma, chi, h, dt, lam, mu, p):
     """Intermediate stress (Eq. sig_star_qs) and the updated chi (Eq. chi_evo).
 
     v: node velocity at step n (walls included), sigma: Voigt cell stress,
-    chi: cell effective temperature.  Returns (sigma_star, chi_next).
+    chi: cell effective temperature.  Returns (sigma_star, chi_next).  With
+    p["l_diff"] = l > 0 the diffusion term l^2 div(D^pl grad chi) joins the
+    chi step.
     """
-    return stz_pointwise(grad_cell(v, h), sigma, chi, dt, lam, mu, p)
+    sstar, chi_next = stz_pointwise(grad_cell(v, h), sigma, chi, dt, lam, mu, p)
+    l = p.get("l_diff", 0.0)
+    if l > 0.0:
+        chi_next = chi_next + (dt / p["c0"]) * (l * l) * chi_diffusion(sigma, chi, h, p)
+    return sstar, chi_next
 
 
 def rhs(sigma_star, h, dt):

@@ -677,7 +677,8 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol, in
 namespace {
 
 bool valid_stz(const qs_stz_params* sp) {
-  return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt);
+  return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt) &&
+         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff);
 }
 
 StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
@@ -692,6 +693,7 @@ StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
   a.lam = hd->p.lambda;
   a.mu = hd->p.mu;
   a.h = hd->p.h;
+  a.l2 = sp->l_diff * sp->l_diff;
   return a;
 }
 
@@ -712,6 +714,7 @@ qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v, c
                       const double* chi, double* sigma_star, double* chi_next) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !sigma_star || !chi_next) return QS_ERR_ARG;
   if (sigma_star == sigma || chi_next == chi) return QS_ERR_ARG;
+  if (sp->l_diff > 0.0 && hd->L[0].d.nz < 2) return QS_ERR_SHAPE;  // ghost layers need two cells
   launch_stz_step(v, sigma, chi, sigma_star, chi_next, hd->L[0].d, stz_args(hd, sp), hd->stream);
   return launch_check();
 }
@@ -744,6 +747,7 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
     return QS_ERR_ARG;
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
   const Dims d = hd->L[0].d;
+  if (sp->l_diff > 0.0 && d.nz < 2) return QS_ERR_SHAPE;
   Carver cv{static_cast<char*>(scratch)};
   double* sstar = cv.take<double>(6 * cells(d));
   double* chi1 = cv.take<double>(cells(d));
@@ -767,7 +771,7 @@ qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* 
                           const double* g_chi1, double* g_sigma, double* g_chi, double* g_v,
                           void* scratch) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !g_sstar || !g_chi1 || !g_sigma || !g_chi ||
-      !g_v || !scratch)
+      !g_v || !scratch || sp->l_diff != 0.0)
     return QS_ERR_ARG;
   const Dims d = hd->L[0].d;
   double* gL = static_cast<double*>(scratch);

@@ -141,6 +141,7 @@ void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, do
 struct StzArgs {
   double s_y, tau0, beta, delta_over_T, c0, chi_inf, dt;
   double lam, mu, h;
+  double l2;  // squared diffusion length of Eq. chi_evo (0: no diffusion term)
 };
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
                      double* chi1, Dims d, const StzArgs& a, hipStream_t s);

@@ -100,6 +100,75 @@ __device__ __forceinline__ void deviator(const double S[3][3], double S0[3][3], 
   *sbar = sqrt(0.5 * q);
 }
 
+// D^pl of a cell of step n, and of the ghost cell beyond a z wall: sigma and
+// chi linearly extrapolated from the wall cell o0 and its inner neighbour o1.
+// D^pl is 0 where chi is not positive (possible only for an extrapolation).
+__device__ __forceinline__ double dpl_of(const double S[3][3], double x, const StzArgs& a) {
+  double S0[3][3], sb;
+  deviator(S, S0, &sb);
+  return x > 0.0 ? plastic_rate(sb, x, a).D : 0.0;
+}
+
+__device__ __forceinline__ double dpl_cell(const double* __restrict__ sigma,
+                                           const double* __restrict__ chi, int N, int o,
+                                           const StzArgs& a) {
+  double S[3][3];
+  load_voigt(sigma, N, o, S);
+  return dpl_of(S, chi[o], a);
+}
+
+__device__ __forceinline__ double dpl_ghost(const double* __restrict__ sigma,
+                                            const double* __restrict__ chi, int N, int o0, int o1,
+                                            const StzArgs& a, double* xg) {
+  double S[3][3];
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const double val = 2.0 * sigma[n * N + o0] - sigma[n * N + o1];
+    S[VA[n]][VB[n]] = val;
+    S[VB[n]][VA[n]] = val;
+  }
+  *xg = 2.0 * chi[o0] - chi[o1];
+  return dpl_of(S, *xg, a);
+}
+
+// div(D^pl grad chi) at cell c (Eq. chi_evo): flux form over the six faces,
+// face coefficient (D_c + D_n)/2, in the order y+1, y-1, x+1, x-1, z-1, z+1.
+__device__ __forceinline__ double chi_flux_divergence(const double* __restrict__ sigma,
+                                                      const double* __restrict__ chi, int nx,
+                                                      int ny, int nz, const CellIdx& c, int o,
+                                                      double Dc, double xc, const StzArgs& a) {
+  const int N = nx * ny * nz, P = nx * ny;
+  const int im = c.i == 0 ? nx - 1 : c.i - 1, jm = c.j == 0 ? ny - 1 : c.j - 1;
+  const int base = c.k * P;
+  const int nb[4] = {base + c.jp * nx + c.i, base + jm * nx + c.i, base + c.j * nx + c.ip,
+                     base + c.j * nx + im};
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double Dn = dpl_cell(sigma, chi, N, nb[q], a);
+    s += 0.5 * (Dc + Dn) * (chi[nb[q]] - xc);
+  }
+  double xn, Dn;
+  if (c.k > 0) {
+    Dn = dpl_cell(sigma, chi, N, o - P, a);
+    xn = chi[o - P];
+  } else {
+    Dn = dpl_ghost(sigma, chi, N, o, o + P, a, &xn);
+  }
+  s += 0.5 * (Dc + Dn) * (xn - xc);
+  if (c.k < nz - 1) {
+    Dn = dpl_cell(sigma, chi, N, o + P, a);
+    xn = chi[o + P];
+  } else {
+    Dn = dpl_ghost(sigma, chi, N, o, o - P, a, &xn);
+  }
+  s += 0.5 * (Dc + Dn) * (xn - xc);
+  return s / (a.h * a.h);
+}
+
+// DIFF: with the diffusion term of Eq. chi_evo (l > 0); each cell evaluates
+// D^pl of its six neighbours itself, from sigma and chi of step n.
+template <bool DIFF>
 __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
                                                   const double* __restrict__ sigma,
                                                   const double* __restrict__ chi,
@@ -131,7 +200,13 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
     const double rate = LS + SLt - trL * S[p][q] - 2.0 * a.mu * rho * S0[p][q];
     sstar[n * N + t] = S[p][q] + a.dt * rate;
   }
-  chi1[t] = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
+  double xn = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
+  if (DIFF) {
+    // the cell's own D^pl as in the flux form (0 where chi is not positive)
+    const double Dc = x > 0.0 ? pl.D : 0.0;
+    xn = xn + (a.dt / a.c0) * a.l2 * chi_flux_divergence(sigma, chi, nx, ny, nz, c, t, Dc, x, a);
+  }
+  chi1[t] = xn;
 }
 
 // Node divergence of a cell field (corner form of Eq. stag_stenc): for
@@ -461,8 +536,12 @@ inline int blocks_for(long long n, int bs) { return static_cast<int>((n + bs - 1
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
                      double* chi1, Dims d, const StzArgs& a, hipStream_t s) {
   const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
-  hipLaunchKernelGGL(k_stz_step, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi, sstar,
-                     chi1, d.nx, d.ny, d.nz, a);
+  if (a.l2 > 0.0)
+    hipLaunchKernelGGL(k_stz_step<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi,
+                       sstar, chi1, d.nx, d.ny, d.nz, a);
+  else
+    hipLaunchKernelGGL(k_stz_step<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi,
+                       sstar, chi1, d.nx, d.ny, d.nz, a);
 }
 
 void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s) {

@@ -61,6 +61,50 @@ def test_stz_step(n):
         assert rel(host(c1) - chi, rc - chi) < 1e-11
 
 
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20), (32, 32, 16)])
+def test_stz_step_with_chi_diffusion(n):
+    """The diffusion term of Eq. chi_evo (l = h and l = 1.5 h, the paper's two
+    choices): the chi update, to whose increment the flux term adds about a
+    fifth in a smooth state just above yield, matches the oracle's; sigma* is
+    unchanged by it.  Wall-adjacent layers use the extrapolated ghost cells."""
+    rng = np.random.default_rng(3)
+    nx, ny, nz = n
+    h = 1.0 / nz
+    g = solver(nx, ny, nz)
+    v, _, _ = random_state(rng, nx, ny, nz)
+    # smooth fields, as the extrapolated ghost layers assume: shear stress just
+    # above yield with a smooth modulation, and a Gaussian defect of higher chi
+    # at the centre as in the paper's runs
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5 - nz / 2) * h, (np.arange(ny) + 0.5 - ny / 2) * h,
+                          (np.arange(nx) + 0.5 - nx / 2) * h, indexing="ij")
+    sig = np.zeros((6, nz, ny, nx))
+    sig[4] = P["s_y"] * (1.03 + 0.01 * np.sin(2 * np.pi * x * nz / nx) * np.cos(np.pi * z))
+    sig[0] = 1e-3 * np.cos(2 * np.pi * y * nz / ny)
+    chi = 0.05 + 0.008 * np.exp(-200.0 * (x * x + y * y + z * z))
+    for l in (h, 1.5 * h):
+        p = dict(P, l_diff=l)
+        dt = 10.0
+        ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
+        rs, rc = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
+        assert rel(host(ss), rs) < 1e-12
+        assert rel(host(c1) - chi, rc - chi) < 1e-11
+        term = ostz.chi_diffusion(sig, chi, h, P)
+        assert np.abs(term).max() * (dt / P["c0"]) * l * l > 0.05 * np.abs(rc - chi).max()
+
+
+def test_reverse_mode_refuses_chi_diffusion():
+    """The reverse-mode STZ step is written for l = 0 and refuses l > 0."""
+    from paper_1904_03808_amd._capi import QSError
+    rng = np.random.default_rng(4)
+    nx, ny, nz = 8, 8, 8
+    g = solver(nx, ny, nz)
+    v, sig, chi = random_state(rng, nx, ny, nz)
+    z = lambda *s: torch.zeros(s, dtype=torch.float64, device="cuda")
+    with pytest.raises(QSError):
+        g.stz_step_vjp(dict(P, l_diff=0.1), 1.0, dev(v), dev(sig), dev(chi), z(6, nz, ny, nx),
+                       z(nz, ny, nx), z(3, nz + 1, ny, nx))
+
+
 @pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20)])
 def test_rhs_and_stress_update(n):
     rng = np.random.default_rng(1)

@@ -140,3 +140,69 @@ def test_chi_field_statistics():
     chi = chi_field(96, 96, 96, seed=3, mean=0.05, std=0.003, lc_cells=4.0)
     assert abs(chi.mean() - 0.05) < 2e-4
     assert abs(chi.std() / 0.003 - 1.0) < 0.08
+
+
+def test_chi_diffusion_operator_closed_forms():
+    """The 7-point flux form of div(D grad chi) (Eq. chi_evo): for constant D
+    a Fourier mode in x and y is an eigenfunction with eigenvalue
+    D (2 cos(2 pi m/nx) - 2 + 2 cos(2 pi q/ny) - 2) / h^2; a field linear in z
+    (its linearly extrapolated ghosts continue it) and a constant field give
+    zero for any D."""
+    nx, ny, nz, h = 12, 10, 6, 0.1
+    rng = np.random.default_rng(5)
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    kz = np.arange(nz + 2)[:, None, None]
+    D = 0.7
+    m, q = 3, 2
+    mode = np.cos(2 * np.pi * m * i / nx) * np.cos(2 * np.pi * q * j / ny) * (1.0 + 0 * kz)
+    out = stz.flux_divergence(np.full(mode.shape, D), mode, h)
+    lam_ = D * ((2 * np.cos(2 * np.pi * m / nx) - 2) + (2 * np.cos(2 * np.pi * q / ny) - 2)) / h**2
+    assert np.abs(out - lam_ * mode[1:-1]).max() <= 1e-12 * abs(lam_)
+    zlin = stz.z_ghosts(np.broadcast_to(0.3 + 0.05 * np.arange(nz)[:, None, None], (nz, ny, nx)))
+    assert np.abs(zlin[0] - 0.25).max() < 1e-15 and np.abs(zlin[-1] - (0.3 + 0.05 * nz)).max() < 1e-15
+    out = stz.flux_divergence(np.full(zlin.shape, D), zlin, h)
+    assert np.abs(out).max() <= 1e-12
+    Dr = rng.uniform(0.1, 1.0, (nz + 2, ny, nx))
+    assert np.abs(stz.flux_divergence(Dr, np.full(Dr.shape, 0.04), h)).max() == 0.0
+
+
+def test_chi_diffusion_flux_form_is_conservative_in_x_and_y():
+    """With D and chi constant in z, the z faces carry no flux, and the x and y
+    faces are shared by two cells with opposite signs, so the cell sum of
+    div(D grad chi) over a periodic x-y plane vanishes for any D, chi."""
+    rng = np.random.default_rng(6)
+    nx, ny, nz = 9, 7, 4
+    Dp = rng.uniform(0.1, 1.0, (1, ny, nx))
+    cp = rng.uniform(0.02, 0.06, (1, ny, nx))
+    D = np.repeat(Dp, nz + 2, axis=0)
+    c = np.repeat(cp, nz + 2, axis=0)
+    out = stz.flux_divergence(D, c, 0.2)
+    assert np.abs(out.sum(axis=(1, 2))).max() <= 1e-12 * np.abs(out).max()
+
+
+def test_chi_step_with_diffusion_adds_the_flux_term():
+    """stz_step with l > 0 adds (dt/c0) l^2 div(D^pl grad chi) to the chi of
+    the l = 0 step, with D^pl evaluated on sigma and chi of step n (ghost
+    layers by linear extrapolation); above yield the term is nonzero."""
+    rng = np.random.default_rng(7)
+    nx, ny, nz = 8, 6, 5
+    h = 1.0 / nz
+    v = shear_velocity(nx, ny, nz, 1e-5)
+    sigma = np.zeros((6, nz, ny, nx))
+    sigma[4] = P["s_y"] * rng.uniform(1.02, 1.06, (nz, ny, nx))
+    chi = chi_field(nx, ny, nz, 3, 0.05, 0.003, 2.0)
+    p0 = dict(P)
+    p1 = dict(P, l_diff=h)
+    dt = 10.0
+    s0, c0 = stz.stz_step(v, sigma, chi, h, dt, LAM, MU, p0)
+    s1, c1 = stz.stz_step(v, sigma, chi, h, dt, LAM, MU, p1)
+    assert np.array_equal(s0, s1)
+    term = stz.chi_diffusion(sigma, chi, h, P)
+    assert np.abs(term).max() > 0.0
+    # (the difference of two chi values carries their rounding, 1e-16 absolute)
+    assert np.allclose(c1 - c0, (dt / P["c0"]) * h * h * term, rtol=1e-12, atol=1e-16)
+    # the ghost layer of a cell next to a wall: D^pl of the extrapolated state
+    sg, cg = stz.z_ghosts(sigma), stz.z_ghosts(chi)
+    assert np.allclose(sg[:, 0], 2 * sigma[:, 0] - sigma[:, 1])
+    assert np.allclose(cg[-1], 2 * chi[-1] - chi[-2])
