@@ -251,6 +251,97 @@ def config4_adjoint(n: int = 96, steps: int = 10) -> dict:
             "loss": loss.item(), "solver": "fp64, rtol 1e-10 forward and transposed"}
 
 
+def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
+    """The single-defect run of Sec. 4.4 on its N x N x N/2 grid (h = L/(N/2)):
+    chi from Eq. case0_chi, l = h, dt = 200 t_s, U = 1e-7 L/t_s, the sample at
+    rest and free of stress at t = 0.  `steps` FP32-IR projection steps
+    (rtol 1e-10, warm-started) are timed between device synchronisations, with
+    a split every 500 steps: elastic loading (to t = 1e5 t_s), yield, then
+    plastic flow concentrating in the defect.  1500 steps stay below the point
+    (t near 3.7e5 t_s) where the single forward-Euler step of the plastic
+    term loses stability in the defect.  Then the time per V-cycle at this
+    shape, FP32-IR and FP64, from solves from zero of a D_h sigma right-hand
+    side (seed 2): the figure the paper tabulates (Tables 2 and 3, and the
+    single-defect run's V-cycle total)."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import defect_state, lame, stress_field_device, stz_constants
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    nx, ny, nz = N, N, N // 2
+    h = 1.0 / nz
+    P, dt, U = dict(stz_constants(), l_diff=h), 200.0, 1e-7
+    st = defect_state(nx, ny, nz, U)
+    g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=min_coarse_nz, precision="fp32-ir",
+                 device=dev)
+    v0, s0, c0 = (torch.from_numpy(st[k]).to(dev) for k in ("v", "sigma", "chi"))
+    del st
+    v, s, c = v0.clone(), s0.clone(), c0.clone()
+    g.projection_step(P, dt, U, v, s, c, rtol=1e-10)  # warm-up (state discarded)
+    v.copy_(v0), s.copy_(s0), c.copy_(c0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    marks, cycles = [t0], []
+    # U(t) ramps to U_B over the first t_s < dt, so every step sees U_B
+    for i in range(steps):
+        cycles.append(g.projection_step(P, dt, U, v, s, c, rtol=1e-10).cycles)
+        if (i + 1) % 500 == 0 or i + 1 == steps:
+            torch.cuda.synchronize()
+            marks.append(time.perf_counter())
+    ms = (marks[-1] - t0) * 1e3 / steps
+    phases = []
+    for m in range(len(marks) - 1):
+        a, b = 500 * m, min(500 * (m + 1), steps)
+        phases.append({"steps": [a, b], "ms_per_step": (marks[m + 1] - marks[m]) * 1e3 / (b - a),
+                       "vcycles_per_step": sum(cycles[a:b]) / (b - a)})
+    p_ = (s[0] + s[1] + s[2]) / 3
+    sbar = torch.sqrt(0.5 * ((s[0] - p_) ** 2 + (s[1] - p_) ** 2 + (s[2] - p_) ** 2)
+                      + s[3] ** 2 + s[4] ** 2 + s[5] ** 2)
+    state = {"t_end": steps * dt, "sbar_max_over_sY": (sbar.max() / P["s_y"]).item(),
+             "sbar_mean_over_sY": (sbar.mean() / P["s_y"]).item(),
+             "chi_max_K": c.max().item() * 21000.0, "chi_min_K": c.min().item() * 21000.0}
+    levels = g.levels
+    g.close()
+    del v0, s0, c0, v, s, c, sbar, p_
+    sig = stress_field_device(nx, ny, nz, 2, dev)
+    gr = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=min_coarse_nz, precision="fp64",
+                  device=dev)
+    b = gr.rhs(sig, 1.0)
+    gr.close()
+    del sig
+    per_cycle = {}
+    for name, prec in (("fp32_ir", "fp32-ir"), ("fp64", "fp64")):
+        gs = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=min_coarse_nz, precision=prec,
+                      device=dev)
+        x = torch.zeros_like(b)
+        gs.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            x.zero_()
+            info = gs.solve(b, x, rtol=1e-10)
+        torch.cuda.synchronize()
+        dts = (time.perf_counter() - t1) / reps
+        per_cycle[name] = {"ms_per_solve": dts * 1e3, "cycles": info.cycles,
+                           "ms_per_vcycle": dts * 1e3 / max(info.cycles, 1)}
+        gs.close()
+    del b, x
+    torch.cuda.empty_cache()
+    return {"grid": [nx, ny, nz], "levels": levels, "min_coarse_nz": min_coarse_nz,
+            "steps": steps, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
+            "vcycles": sum(cycles), "vcycles_per_step": sum(cycles) / steps,
+            "max_vcycles_in_a_step": max(cycles), "phases": phases, "state_at_end": state,
+            "solver": "fp32-ir, rtol 1e-10", "per_vcycle_from_zero": per_cycle,
+            "inputs": "chi Eq. case0_chi (550 K + 170 K Gaussian), sigma = 0, v = 0 at t = 0; "
+                      "l = h, dt = 200 t_s, U = 1e-7 L/t_s",
+            "paper_context_32_cpu_processes": {
+                "s_per_vcycle_table3": 0.76, "s_per_vcycle_table2": 0.55,
+                "single_defect_run": {"steps": 5000, "hours": 7.52, "vcycle_hours": 5.852,
+                                      "vcycles": 17586}}}
+
+
 def profile_solve(n: int) -> None:
     """Kernels for hardware-counter runs of a whole V-cycle: two FP32-IR cycles
     (fixed count, no convergence test) of the n^3 bench system."""
@@ -308,6 +399,13 @@ def main():
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 comparison block")
     ap.add_argument("--no-steps", action="store_true",
                     help="skip the shear-step (256^3) and adjoint (96^3) blocks")
+    ap.add_argument("--no-defect", action="store_true",
+                    help="skip the single-defect block (256 x 256 x 128)")
+    ap.add_argument("--defect-steps", type=int, default=1500,
+                    help="projection steps of the single-defect block (the paper's run has 5000; "
+                         "beyond about 1850 the forward-Euler plastic step is unstable)")
+    ap.add_argument("--defect-only", action="store_true",
+                    help="only run the single-defect block and print it")
     ap.add_argument("--profile-solve", action="store_true",
                     help="only run two FP32-IR V-cycles (for rocprofv3 counters)")
     ap.add_argument("--profile-smoother", action="store_true",
@@ -329,6 +427,9 @@ def main():
         return
     if args.profile_solve:
         profile_solve(args.n)
+        return
+    if args.defect_only:
+        print(json.dumps({"defect_256x256x128": defect_run(steps=args.defect_steps)}))
         return
     n = args.n
     h = 1.0 / n
@@ -419,6 +520,8 @@ def main():
     if not args.no_steps and n == 256:
         out["config3_shear_256"] = config3_shear()
         out["config4_adjoint_96"] = config4_adjoint()
+    if not args.no_defect and n == 256:
+        out["defect_256x256x128"] = defect_run(steps=args.defect_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, results["fp64"]["cycles"])
     print(json.dumps(out))

@@ -7,7 +7,7 @@ torch = pytest.importorskip("torch")
 from oracle import stz as ostz
 from oracle.multigrid import MGOracle
 from oracle.operators import div_node
-from workloads import chi_field, lame, shear_state, stz_constants
+from workloads import chi_field, defect_state, lame, shear_state, stz_constants
 
 pytestmark = pytest.mark.gpu
 LAM, MU = lame()
@@ -136,3 +136,34 @@ def test_projection_steps(prec):
         assert rel(host(vd), v) < tol, step
         assert rel(host(sd), sig) < tol, step
         assert rel(host(cd), chi) < 1e-13, step
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
+def test_projection_steps_single_defect(prec):
+    """Three steps of the single-defect run (Sec. 4.4: chi from Eq. case0_chi,
+    l = h, dt = 200 t_s, U = 1e-7 L/t_s) on its N x N x N/2 shape at N = 32,
+    with three multigrid levels down to 8 x 8 x 4.  The sample is preloaded with sigma_xz just above yield, so that the plastic
+    terms and the chi diffusion act from the first step (the paper starts
+    from rest)."""
+    nx, ny, nz, dt, U = 32, 32, 16, 200.0, 1e-7
+    h = 1.0 / nz
+    p = dict(P, l_diff=h)
+    st = defect_state(nx, ny, nz, U)
+    v, sig, chi = st["v"], st["sigma"], st["chi"]
+    sig[4] = 1.01 * P["s_y"]
+    g = solver(nx, ny, nz, precision=prec, min_coarse_nz=4)
+    assert g.levels == 3
+    o = MGOracle(nx, ny, nz, h, LAM, MU)
+    vd, sd, cd = dev(v), dev(sig), dev(chi)
+    for step in range(3):
+        info = g.projection_step(p, dt, U, vd, sd, cd, rtol=1e-12)
+        c0 = chi
+        v, sig, chi, oi = ostz.projection_step(v, sig, chi, h, dt, LAM, MU, p, U, o, rtol=1e-12)
+        assert info.converged
+        assert rel(host(vd), v) < 1e-10, step
+        assert rel(host(sd), sig) < 1e-10, step
+        assert rel(host(cd), chi) < 1e-13, step
+        # the increment goes through exp(beta s) with beta s near 14, which
+        # magnifies the 1e-10-level differences of the two solves' sigma
+        assert rel(host(cd) - c0, chi - c0) < 1e-8, step
+    assert np.abs(chi - st["chi"]).max() > 0

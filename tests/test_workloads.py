@@ -26,3 +26,24 @@ def test_device_stress_recipe_matches_host_recipe():
     host = W.stress_field(10, 8, 6, 5)
     assert host.shape == dev.shape and np.isfinite(host).all()
     assert abs(host.std() - dev.std()) < 0.2
+
+
+def test_defect_chi_follows_eq_case0_chi():
+    """Eq. case0_chi on the paper's N x N x N/2 grid shape: the defect sits at
+    the sample's centre, so the field is mirror-symmetric in every direction;
+    the cells next to the centre (distance h sqrt(3)/2 from it) carry the
+    largest value, and far from it the field falls to 550 K."""
+    nx, ny, nz = 32, 32, 16
+    chi = W.defect_chi(nx, ny, nz) * 21000.0
+    assert chi.shape == (nz, ny, nx)
+    assert np.array_equal(chi, chi[::-1]) and np.array_equal(chi, chi[:, ::-1])
+    assert np.array_equal(chi, chi[:, :, ::-1])
+    h = 1.0 / nz
+    top = 550.0 + 170.0 * np.exp(-200.0 * 3 * (h / 2) ** 2)
+    assert np.isclose(chi.max(), top, rtol=0, atol=1e-12)
+    assert np.array_equal(np.argwhere(chi == chi.max()).min(0), [nz // 2 - 1, ny // 2 - 1, nx // 2 - 1])
+    # the corner cell: |x|^2 = (L - h/2)^2 + 2 (2L/2 - h/2)^2 with L = 1
+    corner = 550.0 + 170.0 * np.exp(-200.0 * ((0.5 - h / 2) ** 2 + 2 * (1.0 - h / 2) ** 2))
+    assert np.isclose(chi[0, 0, 0], corner, rtol=1e-14) and chi[0, 0, 0] - 550.0 < 1e-40
+    st = W.defect_state(nx, ny, nz)
+    assert not st["v"].any() and not st["sigma"].any()

@@ -141,6 +141,22 @@ def chi_field(nx: int, ny: int, nz: int, seed: int, mean: float = 0.05,
     return np.ascontiguousarray(mean + std * out / norm)
 
 
+def defect_chi(nx: int, ny: int, nz: int, base_K: float = 550.0, amp_K: float = 170.0,
+               width: float = 200.0, ez_K: float = 21000.0) -> np.ndarray:
+    """Single Gaussian defect of higher effective temperature at the centre of
+    the sample (paper Sec. 4.4, Eq. case0_chi): base + amp exp(-width |x|^2/L^2)
+    in kelvin, converted to units of e_z/k_B.  The sample spans nx h by ny h by
+    nz h with h = 1/nz, so L = nz h (the paper's 2L x 2L x L sample on an
+    N x N x N/2 grid when nx = ny = 2 nz); |x| is measured from the sample's
+    centre to the cell centres."""
+    h = 1.0 / nz
+    zc = (np.arange(nz) + 0.5 - 0.5 * nz) * h
+    yc = (np.arange(ny) + 0.5 - 0.5 * ny) * h
+    xc = (np.arange(nx) + 0.5 - 0.5 * nx) * h
+    r2 = zc[:, None, None] ** 2 + yc[None, :, None] ** 2 + xc[None, None, :] ** 2
+    return (base_K + amp_K * np.exp(-width * r2)) / ez_K
+
+
 # ---------------------------------------------------------------------------
 # Manufactured velocity: periodic sin/cos in x, y, polynomial in z vanishing
 # at both walls.  f = -div(C : grad u) is its exact (continuous) source term.
@@ -203,6 +219,14 @@ def shear_velocity(nx: int, ny: int, nz: int, U: float) -> np.ndarray:
     zk = np.arange(nz + 1) / nz
     v[0] = (U * (2.0 * zk - 1.0))[:, None, None]
     return v
+
+
+def defect_state(nx: int, ny: int, nz: int, U: float = 1e-7) -> dict:
+    """Initial (v, sigma, chi) of the single-defect run (paper Sec. 4.4): the
+    sample at rest and free of stress, chi from Eq. case0_chi.  The wall speed
+    ramps up over the first t_s (Eq. u_bc), so at t = 0 the walls are still."""
+    return dict(v=shear_velocity(nx, ny, nz, 0.0), sigma=np.zeros((6, nz, ny, nx)),
+                chi=defect_chi(nx, ny, nz))
 
 
 def shear_state(nx: int, ny: int, nz: int, seed: int, U: float = 1e-5,
