@@ -181,6 +181,32 @@ def test_chi_diffusion_flux_form_is_conservative_in_x_and_y():
     assert np.abs(out.sum(axis=(1, 2))).max() <= 1e-12 * np.abs(out).max()
 
 
+def test_chi_diffusion_operator_is_symmetric_negative_semidefinite():
+    """For D^pl varying in x and y (constant in z, so no z flux), the map
+    chi -> div(D grad chi) on a periodic plane is a weighted graph Laplacian:
+    symmetric (each face coefficient is shared by its two cells), negative
+    semidefinite, with the constants in its null space.  Using D of one cell
+    instead of the face mean, or a shifted neighbour index, breaks the
+    symmetry."""
+    rng = np.random.default_rng(8)
+    nx, ny, nz = 5, 4, 3
+    Dp = rng.uniform(0.1, 1.0, (ny, nx))
+    D = np.broadcast_to(Dp, (nz + 2, ny, nx)).copy()
+    M = np.zeros((ny * nx, ny * nx))
+    for q in range(ny * nx):
+        e = np.zeros(ny * nx)
+        e[q] = 1.0
+        c = np.broadcast_to(e.reshape(ny, nx), (nz + 2, ny, nx)).copy()
+        out = stz.flux_divergence(D, c, 0.5)
+        assert np.abs(out - out[0]).max() == 0.0
+        M[:, q] = out[0].ravel()
+    assert np.abs(M - M.T).max() <= 1e-14
+    assert np.linalg.eigvalsh(M).max() <= 1e-12
+    assert np.abs(M.sum(axis=1)).max() <= 1e-13
+    # a face's coefficient is the mean of its two cells' D
+    assert np.isclose(M[0, 1], (Dp[0, 0] + Dp[0, 1]) / 2 / 0.25)
+
+
 def test_chi_step_with_diffusion_adds_the_flux_term():
     """stz_step with l > 0 adds (dt/c0) l^2 div(D^pl grad chi) to the chi of
     the l = 0 step, with D^pl evaluated on sigma and chi of step n (ghost
