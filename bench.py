@@ -342,6 +342,59 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
                                       "vcycles": 17586}}}
 
 
+TABLE3_S_PER_VCYCLE = {128: 0.22, 256: 0.76, 384: 2.08, 512: 3.87, 768: 13.88}
+
+
+def table3_shapes(Ns=(128, 256, 384, 512, 768), reps: int = 3) -> dict:
+    """Time per V-cycle on the paper's N x N x N/2 grids (Table 3: N = 128 to
+    768, h = L/(N/2)), FP32-IR and FP64: solves from zero of b = D_h sigma
+    (smoothed random stress generated on the device, seed 2) to 1e-10, `reps`
+    timed after one warm-up, divided by the cycles taken.  Coarsening stops at
+    nz <= 4 (8 x 8 x 4 or 6 x 6 x 3 coarsest)."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, stress_field_device
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    out = {}
+    for N in Ns:
+        nx, ny, nz = N, N, N // 2
+        h = 1.0 / nz
+        sig = stress_field_device(nx, ny, nz, 2, dev)
+        g64 = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=4, precision="fp64", device=dev)
+        b = g64.rhs(sig, 1.0)
+        del sig
+        row = {"grid": [nx, ny, nz], "levels": g64.levels,
+               "paper_s_per_vcycle_32_cpu_processes": TABLE3_S_PER_VCYCLE.get(N)}
+        for name, prec in (("fp32_ir", "fp32-ir"), ("fp64", "fp64")):
+            g = g64 if prec == "fp64" else MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=4,
+                                                    precision=prec, device=dev)
+            x = torch.zeros_like(b)
+            g.solve(b, x, rtol=1e-10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                x.zero_()
+                info = g.solve(b, x, rtol=1e-10)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / reps
+            row[name] = {"ms_per_solve": ms, "cycles": info.cycles, "rel_res": info.rel_res,
+                         "ms_per_vcycle": ms / max(info.cycles, 1)}
+            if g is not g64:
+                g.close()
+            del x
+        g64.close()
+        del b
+        torch.cuda.empty_cache()
+        p = row["paper_s_per_vcycle_32_cpu_processes"]
+        if p:
+            row["paper_over_fp64"] = p * 1e3 / row["fp64"]["ms_per_vcycle"]
+        out["N%d" % N] = row
+        print("table3 shape N=%d done" % N, file=sys.stderr, flush=True)
+    return out
+
+
 def profile_solve(n: int) -> None:
     """Kernels for hardware-counter runs of a whole V-cycle: two FP32-IR cycles
     (fixed count, no convergence test) of the n^3 bench system."""
@@ -406,6 +459,10 @@ def main():
                          "beyond about 1850 the forward-Euler plastic step is unstable)")
     ap.add_argument("--defect-only", action="store_true",
                     help="only run the single-defect block and print it")
+    ap.add_argument("--no-table3", action="store_true",
+                    help="skip the V-cycle timing on the paper's N x N x N/2 grids (N = 128..768)")
+    ap.add_argument("--table3-only", action="store_true",
+                    help="only time V-cycles on the paper's N x N x N/2 grids and print them")
     ap.add_argument("--profile-solve", action="store_true",
                     help="only run two FP32-IR V-cycles (for rocprofv3 counters)")
     ap.add_argument("--profile-smoother", action="store_true",
@@ -427,6 +484,9 @@ def main():
         return
     if args.profile_solve:
         profile_solve(args.n)
+        return
+    if args.table3_only:
+        print(json.dumps({"table3_shapes": table3_shapes()}))
         return
     if args.defect_only:
         print(json.dumps({"defect_256x256x128": defect_run(steps=args.defect_steps)}))
@@ -522,6 +582,8 @@ def main():
         out["config4_adjoint_96"] = config4_adjoint()
     if not args.no_defect and n == 256:
         out["defect_256x256x128"] = defect_run(steps=args.defect_steps)
+    if not args.no_table3 and n == 256:
+        out["table3_shapes"] = table3_shapes()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, results["fp64"]["cycles"])
     print(json.dumps(out))

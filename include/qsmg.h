@@ -185,7 +185,10 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
  *                        cotangent into g_v (node vector; walls untouched);
  *                        `scratch`: device memory of qs_step_scratch_bytes().
  *                        At sbar == s_y the one-sided derivative of the
- *                        elastic branch (D^pl = 0) is used.
+ *                        elastic branch (D^pl = 0) is used.  Refuses l > 0
+ *                        (QS_ERR_ARG) and grids with 9 nz ny nx >= 2^31
+ *                        (QS_ERR_SHAPE: the gradient cotangent is indexed
+ *                        with 32-bit integers as [9][cells]).
  *  qs_rhs_vjp:           g_sstar += D_h^T g_b / dt (g_b interior nodes).
  *  qs_stress_update_vjp: g_v += dt (C : sym G_h)^T g_sigma (interior nodes). */
 qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* v,

@@ -774,6 +774,8 @@ qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* 
       !g_v || !scratch || sp->l_diff != 0.0)
     return QS_ERR_ARG;
   const Dims d = hd->L[0].d;
+  // the velocity-gradient cotangent is stored as [9][cells] with 32-bit indices
+  if (9LL * cells(d) >= (1LL << 31)) return QS_ERR_SHAPE;
   double* gL = static_cast<double*>(scratch);
   const StzArgs a = stz_args(hd, sp);
   launch_stz_step_vjp(v, sigma, chi, g_sstar, g_chi1, g_sigma, g_chi, gL, d, a, hd->stream);
