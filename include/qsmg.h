@@ -178,6 +178,19 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
                              double* v, double* sigma, double* chi, void* scratch,
                              double rtol, int max_cycles, qs_solve_info* info);
 
+/* The same step with wall velocities given node by node, for boundary data
+ * that varies in x and y, such as the spinning discs of the friction-welding
+ * runs (Sec. 5, Eqs. u_weld and v_weld): the planes k = 0 and k = nz of
+ * v^{n+1} are copied from wall_lo and wall_hi, each double[3][ny][nx]
+ * (components x, y, z; device memory, caller-owned, not overlapping v; a
+ * fixed wall is passed as zeros).  The STZ step still sees the walls of v^n.
+ * Errors as qs_projection_step; QS_ERR_ARG also for a null or overlapping
+ * wall array. */
+qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp,
+                                   const double* wall_lo, const double* wall_hi, double* v,
+                                   double* sigma, double* chi, void* scratch, double rtol,
+                                   int max_cycles, qs_solve_info* info);
+
 /* Adjoint building blocks (reverse mode of one step; plain Euclidean inner
  * products on the stored arrays, so Voigt off-diagonals are single entries).
  *  qs_stz_step_vjp:      given g_sstar (6 cells) and g_chi1 (cells), return

@@ -151,15 +151,27 @@ def set_shear_walls(v, U):
     return v
 
 
-def projection_step(v, sigma, chi, h, dt, lam, mu, p, U, solver, rtol=1e-10, max_cycles=100):
+def set_walls(v, lo, hi):
+    """Wall planes k = 0 and k = nz of v replaced by the node data lo, hi
+    (each [3, ny, nx])."""
+    v = v.copy()
+    v[:, 0] = lo
+    v[:, -1] = hi
+    return v
+
+
+def projection_step(v, sigma, chi, h, dt, lam, mu, p, U, solver, rtol=1e-10, max_cycles=100,
+                    walls=None):
     """One quasi-static step n -> n+1 (Sec. 3.3).
 
     `solver` is an oracle multigrid (`MGOracle`) for the same grid; the solve
-    is warm-started from v^n with the new wall values.
+    is warm-started from v^n with the new wall values: those of Eq. u_bc with
+    speed U, or, when `walls` = (lo, hi) is given, that node data (e.g. the
+    spinning discs of Sec. 5).
     """
     sstar, chi_next = stz_step(v, sigma, chi, h, dt, lam, mu, p)
     b = rhs(sstar, h, dt)
-    x0 = set_shear_walls(v, U)
+    x0 = set_shear_walls(v, U) if walls is None else set_walls(v, *walls)
     v_next, info = solver.solve(b, x0, rtol=rtol, max_cycles=max_cycles)
     s_next = stress_update(sstar, v_next, h, dt, lam, mu)
     return v_next, s_next, chi_next, info

@@ -66,6 +66,8 @@ SIGNATURES = {
     "qs_step_scratch_bytes": [_P, C.POINTER(C.c_size_t)],
     "qs_projection_step": [_P, C.POINTER(QSStzParams), _D, _P, _P, _P, _P, _D, _I,
                            C.POINTER(QSSolveInfo)],
+    "qs_projection_step_walls": [_P, C.POINTER(QSStzParams), _P, _P, _P, _P, _P, _P, _D, _I,
+                                 C.POINTER(QSSolveInfo)],
     "qs_stz_step_vjp": [_P, C.POINTER(QSStzParams), _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "qs_rhs_vjp": [_P, _P, _D, _P],
     "qs_stress_update_vjp": [_P, _P, _D, _P],

@@ -739,9 +739,14 @@ qs_status qs_step_scratch_bytes(qs_handle* hd, size_t* bytes) {
   return QS_OK;
 }
 
-qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double* v,
-                             double* sigma, double* chi, void* scratch, double rtol,
-                             int max_cycles, qs_solve_info* info) {
+namespace {
+
+// One projection step; the new wall planes of v are (-U,0,0) / (+U,0,0) when
+// lo is null, else copied from lo and hi.
+qs_status projection_step_impl(qs_handle* hd, const qs_stz_params* sp, double U_wall,
+                               const double* lo, const double* hi, double* v, double* sigma,
+                               double* chi, void* scratch, double rtol, int max_cycles,
+                               qs_solve_info* info) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || max_cycles < 0 ||
       !aligned16(v))
     return QS_ERR_ARG;
@@ -754,7 +759,10 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
   double* b = cv.take<double>(d.elems());
   const StzArgs a = stz_args(hd, sp);
   launch_stz_step(v, sigma, chi, sstar, chi1, d, a, hd->stream);
-  launch_set_walls(v, d, U_wall, hd->stream);
+  if (lo)
+    launch_copy_walls(v, lo, hi, d, hd->stream);
+  else
+    launch_set_walls(v, d, U_wall, hd->stream);
   launch_rhs(sstar, b, d, hd->p.h, sp->dt, hd->stream);
   qs_status st = launch_check();
   if (st != QS_OK) return st;
@@ -764,6 +772,35 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
   QS_HIP(hipMemcpyAsync(chi, chi1, cells(d) * sizeof(double), hipMemcpyDeviceToDevice, hd->stream));
   const qs_status lc = launch_check();
   return lc != QS_OK ? lc : st;
+}
+
+}  // namespace
+
+qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double* v,
+                             double* sigma, double* chi, void* scratch, double rtol,
+                             int max_cycles, qs_solve_info* info) {
+  return projection_step_impl(hd, sp, U_wall, nullptr, nullptr, v, sigma, chi, scratch, rtol,
+                              max_cycles, info);
+}
+
+qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp, const double* wall_lo,
+                                   const double* wall_hi, double* v, double* sigma, double* chi,
+                                   void* scratch, double rtol, int max_cycles,
+                                   qs_solve_info* info) {
+  if (!wall_lo || !wall_hi) return QS_ERR_ARG;
+  if (hd) {
+    // the wall data must not overlap v, whose wall planes are written from it
+    const Dims d = hd->L[0].d;
+    const char* v0 = reinterpret_cast<const char*>(v);
+    const char* v1 = v0 + d.elems() * sizeof(double);
+    const size_t wb = 3 * static_cast<size_t>(d.plane()) * sizeof(double);
+    for (const double* w : {wall_lo, wall_hi}) {
+      const char* w0 = reinterpret_cast<const char*>(w);
+      if (v && w0 < v1 && w0 + wb > v0) return QS_ERR_ARG;
+    }
+  }
+  return projection_step_impl(hd, sp, 0.0, wall_lo, wall_hi, v, sigma, chi, scratch, rtol,
+                              max_cycles, info);
 }
 
 qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* v,

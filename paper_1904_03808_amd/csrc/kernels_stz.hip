@@ -314,6 +314,18 @@ __global__ void k_set_walls(double* __restrict__ v, int nx, int ny, int nz, doub
   v[2 * C + o] = 0.0;
 }
 
+// Wall planes k = 0 and k = nz of v from per-node data lo, hi [3][ny][nx].
+__global__ void k_copy_walls(double* __restrict__ v, const double* __restrict__ lo,
+                             const double* __restrict__ hi, int nx, int ny, int nz) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int P = nx * ny;
+  if (t >= 3 * P) return;
+  const int a = t / P, q = t - a * P;
+  const size_t C = static_cast<size_t>(nz + 1) * P;
+  v[a * C + q] = lo[t];
+  v[a * C + static_cast<size_t>(nz) * P + q] = hi[t];
+}
+
 // ---------------------------------------------------------------------------
 // Reverse mode.  All cotangents are derivatives with respect to the stored
 // numbers (Euclidean inner product on the arrays).
@@ -562,6 +574,11 @@ void launch_stress_update(const double* sstar, const double* v, double* out, Dim
 void launch_set_walls(double* v, Dims d, double U, hipStream_t s) {
   hipLaunchKernelGGL(k_set_walls, dim3(blocks_for(2LL * d.plane(), 256)), dim3(256), 0, s, v, d.nx,
                      d.ny, d.nz, U);
+}
+
+void launch_copy_walls(double* v, const double* lo, const double* hi, Dims d, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_walls, dim3(blocks_for(3LL * d.plane(), 256)), dim3(256), 0, s, v, lo,
+                     hi, d.nx, d.ny, d.nz);
 }
 
 void launch_stz_step_vjp(const double* v, const double* sigma, const double* chi,

@@ -179,6 +179,24 @@ class MGSolver:
         n = min(info.cycles + 1, _capi.QS_HIST)
         return SolveInfo(st, info.cycles, info.levels, info.rel_res, list(info.rel_res_hist[:n]))
 
+    def projection_step_walls(self, params: dict, dt: float, wall_lo, wall_hi, v, sigma, chi,
+                              rtol: float = 1e-10, max_cycles: int = 100) -> SolveInfo:
+        """In-place step n -> n+1 with per-node wall velocities of step n+1:
+        wall_lo, wall_hi are (3, ny, nx) float64 device tensors for the planes
+        k = 0 and k = nz."""
+        cs = self.cell_shape
+        ws = (3, self.ny, self.nx)
+        sp = _stz(params, dt)
+        info = QSSolveInfo()
+        st = self._lib.qs_projection_step_walls(
+            self._h, C.byref(sp), self._chk(wall_lo, ws, "wall_lo"), self._chk(wall_hi, ws, "wall_hi"),
+            self._chk(v, self.node_shape(), "v"), self._chk(sigma, (6,) + cs, "sigma"),
+            self._chk(chi, cs, "chi"), C.c_void_p(self._scratch_buf()), float(rtol),
+            int(max_cycles), C.byref(info))
+        check(st, "qs_projection_step_walls")
+        n = min(info.cycles + 1, _capi.QS_HIST)
+        return SolveInfo(st, info.cycles, info.levels, info.rel_res, list(info.rel_res_hist[:n]))
+
     # -- reverse mode -------------------------------------------------------------
     def stz_step_vjp(self, params: dict, dt: float, v, sigma, chi, g_sstar, g_chi1, g_v):
         """Returns (g_sigma, g_chi) and adds the velocity cotangent into g_v."""

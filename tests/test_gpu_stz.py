@@ -7,7 +7,8 @@ torch = pytest.importorskip("torch")
 from oracle import stz as ostz
 from oracle.multigrid import MGOracle
 from oracle.operators import div_node
-from workloads import chi_field, defect_state, lame, shear_state, stz_constants
+from workloads import (chi_field, defect_state, lame, shear_state, shear_velocity,
+                       stz_constants, weld_walls)
 
 pytestmark = pytest.mark.gpu
 LAM, MU = lame()
@@ -30,6 +31,11 @@ def rel(a, b):
 def solver(nx, ny, nz, **kw):
     from paper_1904_03808_amd.qsmg import MGSolver
     return MGSolver(nx, ny, nz, 1.0 / nz, LAM, MU, **kw)
+
+
+def MGSolver_(nx, ny, nz, h, **kw):
+    from paper_1904_03808_amd.qsmg import MGSolver
+    return MGSolver(nx, ny, nz, h, LAM, MU, **kw)
 
 
 def random_state(rng, nx, ny, nz):
@@ -167,3 +173,72 @@ def test_projection_steps_single_defect(prec):
         # magnifies the 1e-10-level differences of the two solves' sigma
         assert rel(host(cd) - c0, chi - c0) < 1e-8, step
     assert np.abs(chi - st["chi"]).max() > 0
+
+
+@pytest.mark.parametrize("case", [("top", "fp64"), ("both", "fp32-ir")])
+def test_projection_steps_friction_welding(case):
+    """Three steps with the spinning-disc wall data of Sec. 5 (Eqs. u_weld and
+    v_weld; omega = 2 pi / 1e8 t_s, dt = 2e4 t_s, R = 1/3) on the slender
+    N x N x N/4 sample at N = 48 (h = 2L/N, three levels), welded on the top
+    wall or on both; chi from Eq. convolve with mean 450 K, std 15 K,
+    l_c = 5h; sigma_xz preloaded just above yield.  The velocity, stress and
+    chi match the oracle's, and v^{n+1} carries the wall data exactly."""
+    walls_on, prec = case
+    nx, ny, nz = 48, 48, 12
+    h = 2.0 / nx
+    dt, omega = 2e4, 2 * np.pi / 1e8
+    p = dict(P, l_diff=h)
+    lo, hi = weld_walls(nx, ny, nz, omega, h, top=True, bottom=(walls_on == "both"))
+    chi = chi_field(nx, ny, nz, 21, 450.0 / 21000, 15.0 / 21000, 5.0)
+    sig = np.zeros((6, nz, ny, nx))
+    sig[4] = 1.01 * P["s_y"]
+    v = shear_velocity(nx, ny, nz, 0.0)
+    g = MGSolver_(nx, ny, nz, h, precision=prec, min_coarse_nz=4)
+    assert g.levels == 3
+    o = MGOracle(nx, ny, nz, h, LAM, MU, min_coarse_nz=4)
+    vd, sd, cd = dev(v), dev(sig), dev(chi)
+    lod, hid = dev(lo), dev(hi)
+    for step in range(3):
+        info = g.projection_step_walls(p, dt, lod, hid, vd, sd, cd, rtol=1e-12)
+        v, sig, chi, oi = ostz.projection_step(v, sig, chi, h, dt, LAM, MU, p, 0.0, o, rtol=1e-12,
+                                               walls=(lo, hi))
+        assert info.converged
+        vh = host(vd)
+        assert np.array_equal(vh[:, 0], lo) and np.array_equal(vh[:, -1], hi)
+        assert rel(vh, v) < 1e-10, step
+        assert rel(host(sd), sig) < 1e-10, step
+        assert rel(host(cd), chi) < 1e-13, step
+    assert np.abs(v[:, nz // 2]).max() > 1e-3 * omega
+
+
+def test_projection_step_walls_rejects_bad_wall_arrays():
+    """Null wall data and wall data overlapping v are refused with
+    QS_ERR_ARG before any work is enqueued; wrongly shaped tensors are refused
+    by the binding."""
+    import ctypes as C
+
+    from paper_1904_03808_amd import _capi
+    from paper_1904_03808_amd.qsmg import _ptr, _stz
+    nx, ny, nz = 16, 16, 8
+    g = MGSolver_(nx, ny, nz, 1.0 / nz)
+    v = torch.zeros((3, nz + 1, ny, nx), dtype=torch.float64, device="cuda")
+    s = torch.zeros((6, nz, ny, nx), dtype=torch.float64, device="cuda")
+    c = torch.full((nz, ny, nx), 0.05, dtype=torch.float64, device="cuda")
+    w = torch.zeros((3, ny, nx), dtype=torch.float64, device="cuda")
+    sp = _stz(P, 1.0)
+    info = _capi.QSSolveInfo()
+
+    def call(lo, hi):
+        return g._lib.qs_projection_step_walls(
+            g._h, C.byref(sp), C.c_void_p(lo), C.c_void_p(hi), C.c_void_p(_ptr(v)),
+            C.c_void_p(_ptr(s)), C.c_void_p(_ptr(c)), C.c_void_p(g._scratch_buf()), 1e-10, 10,
+            C.byref(info))
+
+    assert call(None, _ptr(w)) == _capi.QS_ERR_ARG
+    assert call(_ptr(w), None) == _capi.QS_ERR_ARG
+    assert call(_ptr(v), _ptr(w)) == _capi.QS_ERR_ARG           # v's own bottom plane
+    assert call(_ptr(w), _ptr(v) + 8 * 100) == _capi.QS_ERR_ARG  # inside v
+    with pytest.raises(ValueError):
+        g.projection_step_walls(P, 1.0, w[:, :4], w, v, s, c)
+    torch.cuda.synchronize()
+    assert not v.any()

@@ -232,3 +232,35 @@ def test_chi_step_with_diffusion_adds_the_flux_term():
     sg, cg = stz.z_ghosts(sigma), stz.z_ghosts(chi)
     assert np.allclose(sg[:, 0], 2 * sigma[:, 0] - sigma[:, 1])
     assert np.allclose(cg[-1], 2 * chi[-1] - chi[-2])
+
+
+def test_projection_step_with_node_walls_reduces_to_the_shear_walls():
+    """Wall data given node by node, equal to the walls of Eq. u_bc, gives the
+    step of the U path bit for bit; other wall data ends up in the wall
+    planes of v^{n+1} exactly, with the interior solving K v = b."""
+    from oracle.multigrid import MGOracle
+    from oracle.operators import apply_elastic
+    from workloads import weld_walls
+    nx, ny, nz = 8, 8, 8
+    h = 1.0 / nz
+    U, dt = 1e-5, 10.0
+    v = shear_velocity(nx, ny, nz, U)
+    sigma = np.zeros((6, nz, ny, nx))
+    sigma[4] = 1.02 * P["s_y"]
+    chi = chi_field(nx, ny, nz, 3, 0.05, 0.003, 2.0)
+    o = MGOracle(nx, ny, nz, h, LAM, MU, min_coarse_nz=4)
+    ref = stz.projection_step(v, sigma, chi, h, dt, LAM, MU, P, U, o, rtol=1e-12)
+    w = stz.set_shear_walls(np.zeros_like(v), U)
+    got = stz.projection_step(v, sigma, chi, h, dt, LAM, MU, P, 0.0, o, rtol=1e-12,
+                              walls=(w[:, 0], w[:, -1]))
+    for a, b in zip(ref[:3], got[:3]):
+        assert np.array_equal(a, b)
+    lo, hi = weld_walls(nx, ny, nz, 1e-4, h, top=True, bottom=True)
+    v1, s1, c1, info = stz.projection_step(v, sigma, chi, h, dt, LAM, MU, P, 0.0, o, rtol=1e-12,
+                                           walls=(lo, hi))
+    assert np.array_equal(v1[:, 0], lo) and np.array_equal(v1[:, -1], hi)
+    sstar, _ = stz.stz_step(v, sigma, chi, h, dt, LAM, MU, P)
+    b = stz.rhs(sstar, h, dt)
+    r = (b - apply_elastic(v1, h, LAM, MU))[:, 1:nz]
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b[:, 1:nz] - apply_elastic(
+        stz.set_walls(np.zeros_like(v), lo, hi), h, LAM, MU)[:, 1:nz])

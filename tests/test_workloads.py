@@ -47,3 +47,36 @@ def test_defect_chi_follows_eq_case0_chi():
     assert np.isclose(chi[0, 0, 0], corner, rtol=1e-14) and chi[0, 0, 0] - 550.0 < 1e-40
     st = W.defect_state(nx, ny, nz)
     assert not st["v"].any() and not st["sigma"].any()
+
+
+def test_weld_walls_follow_the_spinning_disc():
+    """Sec. 5: inside the disc r < R the wall moves as a rigid rotation about
+    the centre (tangential, |u| = omega r, no divergence); the profile is
+    continuous at r = R and falls to 10 % a quarter of the way, in r^2, from
+    the disc's edge to the sample's edge (the property that fixes lambda_w);
+    w = 0; only the welded walls move."""
+    R = 1.0 / 3.0
+    assert np.isclose(W.weld_factor(np.array(R * R + (1 - R * R) / 4), R), 0.1, rtol=1e-14)
+    assert np.isclose(W.weld_factor(np.array(R * R * (1 + 1e-12)), R), 1.0, rtol=1e-9)
+    nx, ny, nz, omega = 64, 64, 16, 2e-3
+    h = 2.0 / nx
+    lo, hi = W.weld_walls(nx, ny, nz, omega, h)
+    assert not lo.any() and not hi[2].any()
+    x = np.arange(nx) * h - 1.0
+    X, Y = np.meshgrid(x, x)
+    r2 = X * X + Y * Y
+    inside = r2 < R * R
+    assert inside.sum() > 100
+    u, v = hi[0], hi[1]
+    assert np.abs(u * X + v * Y)[inside].max() <= 1e-18
+    assert np.allclose(np.hypot(u, v)[inside], omega * np.sqrt(r2[inside]), rtol=1e-13)
+    # discrete divergence of the rigid rotation (central differences) inside
+    du = (np.roll(u, -1, 1) - np.roll(u, 1, 1)) / (2 * h)
+    dv = (np.roll(v, -1, 0) - np.roll(v, 1, 0)) / (2 * h)
+    core = (r2 < (R - 2 * h) ** 2)
+    assert np.abs(du + dv)[core].max() <= 1e-15
+    # the profile outside is the same for u and v, and below 1
+    f = np.hypot(u, v) / (omega * np.sqrt(np.maximum(r2, 1e-300)))
+    assert np.all(f[~inside] < 1.0) and np.all(f[~inside] > 0.0)
+    lo2, hi2 = W.weld_walls(nx, ny, nz, omega, h, top=True, bottom=True)
+    assert np.array_equal(lo2, hi2) and np.array_equal(hi2, hi)

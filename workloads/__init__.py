@@ -229,6 +229,32 @@ def defect_state(nx: int, ny: int, nz: int, U: float = 1e-7) -> dict:
                 chi=defect_chi(nx, ny, nz))
 
 
+def weld_factor(r2: np.ndarray, R: float = 1.0 / 3.0) -> np.ndarray:
+    """Radial profile of the spinning disc (paper Sec. 5, Eqs. u_weld and
+    v_weld): 1 inside r^2 < R^2, exp(-lambda_w (r^2 - R^2)^2) outside, with
+    lambda_w = 16 ln(10) / (1 - R^2)^2."""
+    lam_w = 16.0 * math.log(10.0) / (1.0 - R * R) ** 2
+    return np.where(r2 < R * R, 1.0, np.exp(-lam_w * (r2 - R * R) ** 2))
+
+
+def weld_walls(nx: int, ny: int, nz: int, omega: float, h: float, top: bool = True,
+               bottom: bool = False, R: float = 1.0 / 3.0) -> tuple[np.ndarray, np.ndarray]:
+    """Wall velocities (lo, hi), each (3, ny, nx), of the friction-welding
+    runs (paper Sec. 5): a disc spinning about the z axis through the centre
+    of the wall at angular speed omega, (u, v, w) = f(r^2) omega (-y, x, 0)
+    with (x, y) measured from the centre in units of L = 1 and f the profile
+    of `weld_factor`; the welded walls carry it (the same omega on both when
+    both are welded), a wall that is not welded stays still.  Nodes sit at
+    (i h, j h), so the centre is at (nx h / 2, ny h / 2)."""
+    x = np.arange(nx) * h - 0.5 * nx * h
+    y = np.arange(ny) * h - 0.5 * ny * h
+    X, Y = np.meshgrid(x, y)
+    f = weld_factor(X * X + Y * Y, R)
+    disc = np.stack([-omega * f * Y, omega * f * X, np.zeros_like(X)])
+    still = np.zeros((3, ny, nx))
+    return (disc.copy() if bottom else still), (disc if top else still.copy())
+
+
 def shear_state(nx: int, ny: int, nz: int, seed: int, U: float = 1e-5,
                 s0_frac: float = 0.99, chi_mean: float = 0.05, chi_std: float = 0.003,
                 lc_cells: float = 8.0) -> dict:
