@@ -342,6 +342,55 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
                                       "vcycles": 17586}}}
 
 
+def weld_run(N: int = 256, steps: int = 100, both: bool = True) -> dict:
+    """Friction welding (Sec. 5) on the slender N x N x N/4 sample (h = 2L/N):
+    spinning-disc wall data of Eqs. u_weld and v_weld on both walls
+    (omega = 2 pi / 1e8 t_s, R = 1/3), chi from Eq. convolve with mean 450 K,
+    std 15 K, l_c = 5h, l = h, dt = 2e4 t_s, the sample at rest at t = 0.
+    `steps` FP32-IR projection steps (rtol 1e-10, warm-started) timed between
+    device synchronisations."""
+    import math
+
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import chi_field, lame, stz_constants, weld_walls
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    nx, ny, nz = N, N, N // 4
+    h = 2.0 / N
+    P, dt, omega = dict(stz_constants(), l_diff=h), 2e4, 2 * math.pi / 1e8
+    lo, hi = (torch.from_numpy(w).to(dev) for w in weld_walls(nx, ny, nz, omega, h, True, both))
+    c0 = torch.from_numpy(chi_field(nx, ny, nz, 5, 450.0 / 21000, 15.0 / 21000, 5.0)).to(dev)
+    g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=4, precision="fp32-ir", device=dev)
+    v = torch.zeros(g.node_shape(), dtype=torch.float64, device=dev)
+    s = torch.zeros((6, nz, ny, nx), dtype=torch.float64, device=dev)
+    c = c0.clone()
+    g.projection_step_walls(P, dt, lo, hi, v, s, c, rtol=1e-10)  # warm-up (state discarded)
+    v.zero_(), s.zero_(), c.copy_(c0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cycles = [g.projection_step_walls(P, dt, lo, hi, v, s, c, rtol=1e-10).cycles
+              for _ in range(steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    p_ = (s[0] + s[1] + s[2]) / 3
+    sbar = torch.sqrt(0.5 * ((s[0] - p_) ** 2 + (s[1] - p_) ** 2 + (s[2] - p_) ** 2)
+                      + s[3] ** 2 + s[4] ** 2 + s[5] ** 2)
+    out = {"grid": [nx, ny, nz], "levels": g.levels, "steps": steps, "ms_per_step": ms,
+           "steps_per_s": 1e3 / ms, "vcycles_per_step": sum(cycles) / steps,
+           "max_vcycles_in_a_step": max(cycles), "walls": "both" if both else "top",
+           "state_at_end": {"t_end": steps * dt,
+                            "sbar_max_over_sY": (sbar.max() / P["s_y"]).item()},
+           "solver": "fp32-ir, rtol 1e-10",
+           "inputs": "chi Eq. convolve (450 K, 15 K, l_c = 5h, seed 5), sigma = 0, v = 0 at t = 0; "
+                     "l = h, dt = 2e4 t_s, omega = 2 pi / 1e8 t_s, R = 1/3"}
+    g.close()
+    del v, s, c, c0, lo, hi, sbar, p_
+    torch.cuda.empty_cache()
+    return out
+
+
 TABLE3_S_PER_VCYCLE = {128: 0.22, 256: 0.76, 384: 2.08, 512: 3.87, 768: 13.88}
 
 
@@ -453,12 +502,12 @@ def main():
     ap.add_argument("--no-steps", action="store_true",
                     help="skip the shear-step (256^3) and adjoint (96^3) blocks")
     ap.add_argument("--no-defect", action="store_true",
-                    help="skip the single-defect block (256 x 256 x 128)")
+                    help="skip the single-defect (256 x 256 x 128) and welding (256 x 256 x 64) blocks")
     ap.add_argument("--defect-steps", type=int, default=1500,
                     help="projection steps of the single-defect block (the paper's run has 5000; "
                          "beyond about 1850 the forward-Euler plastic step is unstable)")
     ap.add_argument("--defect-only", action="store_true",
-                    help="only run the single-defect block and print it")
+                    help="only run the single-defect and welding blocks and print them")
     ap.add_argument("--no-table3", action="store_true",
                     help="skip the V-cycle timing on the paper's N x N x N/2 grids (N = 128..768)")
     ap.add_argument("--table3-only", action="store_true",
@@ -489,7 +538,8 @@ def main():
         print(json.dumps({"table3_shapes": table3_shapes()}))
         return
     if args.defect_only:
-        print(json.dumps({"defect_256x256x128": defect_run(steps=args.defect_steps)}))
+        print(json.dumps({"defect_256x256x128": defect_run(steps=args.defect_steps),
+                          "weld_256x256x64": weld_run()}))
         return
     n = args.n
     h = 1.0 / n
@@ -582,6 +632,8 @@ def main():
         out["config4_adjoint_96"] = config4_adjoint()
     if not args.no_defect and n == 256:
         out["defect_256x256x128"] = defect_run(steps=args.defect_steps)
+    if not args.no_defect and n == 256:
+        out["weld_256x256x64"] = weld_run()
     if not args.no_table3 and n == 256:
         out["table3_shapes"] = table3_shapes()
     if not args.no_cpu_baseline:

@@ -94,12 +94,52 @@ def chi_diffusion(sigma, chi, h, p):
     return flux_divergence(D, cg, h)
 
 
+def plastic_rate_slope(sbar, chi, p):
+    """d D^pl / d sbar of Eq. stz_dpl above yield (0 at or below):
+    A (beta sinh(beta sbar) (1 - s_Y/sbar) + cosh(beta sbar) s_Y / sbar^2)
+    with A = exp(-1/chi) exp(-Delta/kT) / tau0."""
+    act = sbar > p["s_y"]
+    sb = np.where(act, sbar, p["s_y"])
+    A = np.exp(-1.0 / chi) * np.exp(-p["delta_over_T"]) / p["tau0"]
+    bs = p["beta"] * sb
+    f = 1.0 - p["s_y"] / sb
+    return np.where(act, A * (p["beta"] * np.sinh(bs) * f + np.cosh(bs) * p["s_y"] / (sb * sb)),
+                    0.0)
+
+
+MAX_SUBSTEPS = 65536
+
+
+def substep_count(sbar, chi, dt, mu, p):
+    """Sub-steps of the local plastic relaxation per cell (see stz_pointwise):
+    n_sub <= 1 gives 1 (the single forward-Euler step of Eq. sig_star_qs),
+    n_sub > 1 gives n_sub, and n_sub = -1 gives ceil(4 mu dt dD^pl/dsbar) at
+    the state of step n, between 1 and MAX_SUBSTEPS, so that each sub-step
+    tau keeps tau 2 mu dD^pl/dsbar <= 1/2 (the explicit step of
+    dsbar/dt = -2 mu D^pl is stable below 2 and monotone below 1)."""
+    n = int(p.get("n_sub", 1))
+    if n == -1:
+        m = np.ceil(4.0 * mu * dt * plastic_rate_slope(sbar, chi, p))
+        return np.clip(np.nan_to_num(m, nan=MAX_SUBSTEPS), 1, MAX_SUBSTEPS).astype(np.int64)
+    return np.full(np.shape(sbar), max(n, 1), dtype=np.int64)
+
+
 def stz_pointwise(L, sigma, chi, dt, lam, mu, p):
     """The cellwise part of the step: (L, sigma, chi) -> (sigma*, chi').
 
     L[a, b] = d v_a / d x_b at the cell, sigma in Voigt order.  Implements
     Eq. sig_star_qs and the forward-Euler step of Eq. chi_evo; complex-safe.
+
+    With p["n_sub"] set (see substep_count) a cell may take M > 1 sub-steps
+    of tau = dt/M for its plastic terms, an extension beyond the paper: the
+    kinematic terms L sigma + sigma L^T - tr(L) sigma are taken once from
+    sigma^n, while the relaxation -2 mu (D^pl/sbar) sigma_0 and the growth
+    term of chi are stepped M times, each from the state the previous
+    sub-step left: sigma* = sigma_M + dt (kinematic terms).  M = 1 is the
+    single step of Eq. sig_star_qs.
     """
+    if int(p.get("n_sub", 1)) not in (0, 1):
+        return _stz_pointwise_substeps(L, sigma, chi, dt, lam, mu, p)
     S = voigt_to_full(sigma)
     S0, sbar = deviator(S)
     Dpl = plastic_rate(sbar, chi, p)
@@ -113,6 +153,27 @@ def stz_pointwise(L, sigma, chi, dt, lam, mu, p):
     # D^pl (tensor) : sigma_0 = (D^pl / sbar) sigma_0 : sigma_0 = 2 sbar D^pl
     chi_next = chi + (dt / p["c0"]) * (2.0 * sbar * Dpl / p["s_y"]) * (p["chi_inf"] - chi)
     return full_to_voigt(Sstar), chi_next
+
+
+def _stz_pointwise_substeps(L, sigma, chi, dt, lam, mu, p):
+    S = voigt_to_full(sigma)
+    _, sbar = deviator(S)
+    M = substep_count(sbar, chi, dt, mu, p)
+    tau = dt / M
+    trL = L[0, 0] + L[1, 1] + L[2, 2]
+    kin = (np.einsum("ab...,bc...->ac...", L, S) + np.einsum("ab...,cb...->ac...", S, L)
+           - trL * S)
+    Sp, xp = S.copy(), np.array(chi, dtype=float)
+    for m in range(int(M.max())):
+        on = m < M
+        S0, sb = deviator(Sp)
+        D = plastic_rate(sb, xp, p)
+        ratio = np.where(D > 0.0, D / np.where(D > 0.0, sb, 1.0), 0.0)
+        Sn = Sp - tau * (2.0 * mu * ratio * S0)
+        xn = xp + (tau / p["c0"]) * (2.0 * sb * D / p["s_y"]) * (p["chi_inf"] - xp)
+        Sp = np.where(on, Sn, Sp)
+        xp = np.where(on, xn, xp)
+    return full_to_voigt(Sp + dt * kin), xp
 
 
 def stz_step(v, sigma, chi, h, dt, lam, mu, p):

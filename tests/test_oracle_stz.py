@@ -264,3 +264,82 @@ def test_projection_step_with_node_walls_reduces_to_the_shear_walls():
     r = (b - apply_elastic(v1, h, LAM, MU))[:, 1:nz]
     assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b[:, 1:nz] - apply_elastic(
         stz.set_walls(np.zeros_like(v), lo, hi), h, LAM, MU)[:, 1:nz])
+
+
+def _relaxation_exact(sbar0, chi0, dt, p):
+    """The local plastic relaxation with L = 0 as an ODE in (sbar, chi):
+    dsbar/dt = -2 mu D^pl, c0 dchi/dt = (2 sbar D^pl / s_Y)(chi_inf - chi)
+    (the deviator keeps its direction), integrated by scipy's Radau."""
+    from scipy.integrate import solve_ivp
+
+    def f(t, y):
+        D = float(stz.plastic_rate(np.array([y[0]]), np.array([y[1]]), p)[0])
+        return [-2.0 * MU * D, (2.0 * y[0] * D / p["s_y"]) * (p["chi_inf"] - y[1]) / p["c0"]]
+
+    r = solve_ivp(f, (0.0, dt), [sbar0, chi0], method="Radau", rtol=1e-12, atol=[1e-16, 1e-16])
+    return r.y[0, -1], r.y[1, -1]
+
+
+def _one_cell(vals, chi, dt, p):
+    sig = _uniform(1, vals)
+    L = np.zeros((3, 3, 1, 1, 1))
+    ss, c1 = stz.stz_pointwise(L, sig, np.full((1, 1, 1), chi), dt, LAM, MU, p)
+    T = voigt_to_full(ss)
+    T0, tbar = stz.deviator(T)
+    return T, T0, float(tbar.ravel()[0]), float(c1.ravel()[0])
+
+
+def test_plastic_substeps_converge_to_the_local_relaxation():
+    """Sub-stepped plastic terms (an extension: the paper takes one step) are
+    forward Euler of the local relaxation ODE, so with L = 0 they converge to
+    its solution at first order in the sub-step, here on a step whose single
+    forward-Euler update is unstable (2 mu dt dD/dsbar = 6); pressure and the
+    deviator's direction are kept."""
+    rng = np.random.default_rng(11)
+    vals = rng.standard_normal(6)
+    S = voigt_to_full(_uniform(1, vals))
+    _, sb = stz.deviator(S)
+    vals = vals * (1.3 * P["s_y"] / float(sb.ravel()[0]))
+    chi = 0.04
+    slope = float(stz.plastic_rate_slope(np.array([1.3 * P["s_y"]]), np.array([chi]), P)[0])
+    dt = 6.0 / (2 * MU * slope)
+    s_ex, c_ex = _relaxation_exact(1.3 * P["s_y"], chi, dt, P)
+    assert P["s_y"] < s_ex < 1.3 * P["s_y"] and chi < c_ex
+    errs = []
+    for M in (64, 128, 256, 512):
+        T, T0, tbar, c1 = _one_cell(vals, chi, dt, dict(P, n_sub=M))
+        errs.append(abs(tbar - s_ex))
+        S0, _ = stz.deviator(voigt_to_full(_uniform(1, vals)))
+        assert np.allclose(T0 / tbar, S0 / (1.3 * P["s_y"]), rtol=1e-12, atol=1e-14)
+        assert np.isclose(np.trace(T).item(), np.trace(voigt_to_full(_uniform(1, vals))).item(),
+                          rtol=1e-14, atol=1e-18)
+        assert abs(c1 - c_ex) <= 20.0 * abs(c_ex - chi) / M
+    ratios = np.array(errs[1:]) / np.array(errs[:-1])
+    assert np.all(ratios > 0.4) and np.all(ratios < 0.6), ratios
+    assert errs[-1] < 2e-3 * (1.3 * P["s_y"] - s_ex)
+    # the single step overshoots below yield on this step
+    _, _, t1, _ = _one_cell(vals, chi, dt, P)
+    assert t1 < P["s_y"]
+
+
+def test_adaptive_substeps_keep_a_stiff_cell_stable():
+    """n_sub = -1: a cell where 2 mu dt dD/dsbar = 400 takes enough sub-steps
+    (each with tau 2 mu dD/dsbar <= 1/2) that sbar decreases monotonically to
+    between s_Y and its start, chi rises toward chi_inf, and both land near
+    the ODE solution; n_sub = 0 and 1 are the paper's single step."""
+    vals = np.array([0.0, 0.0, 0.0, 0.0, 1.25 * P["s_y"], 0.0])
+    chi = 0.04
+    slope = float(stz.plastic_rate_slope(np.array([1.25 * P["s_y"]]), np.array([chi]), P)[0])
+    dt = 400.0 / (2 * MU * slope)
+    M = stz.substep_count(np.array([1.25 * P["s_y"]]), np.array([chi]), dt, MU, dict(P, n_sub=-1))
+    assert M[0] >= 800 and M[0] <= 802
+    _, _, tbar, c1 = _one_cell(vals, chi, dt, dict(P, n_sub=-1))
+    s_ex, c_ex = _relaxation_exact(1.25 * P["s_y"], chi, dt, P)
+    assert P["s_y"] < tbar < 1.25 * P["s_y"] and chi < c1 < P["chi_inf"]
+    assert abs(tbar - s_ex) < 0.01 * (1.25 * P["s_y"] - s_ex)
+    a = _one_cell(vals, chi, dt, dict(P, n_sub=0))
+    b = _one_cell(vals, chi, dt, dict(P, n_sub=1))
+    c = _one_cell(vals, chi, dt, P)
+    assert a[2] == b[2] == c[2] and a[3] == b[3] == c[3]
+    # the single step flips the deviator and leaves it larger than it started
+    assert a[2] > 10 * 1.25 * P["s_y"]
