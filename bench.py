@@ -251,7 +251,8 @@ def config4_adjoint(n: int = 96, steps: int = 10) -> dict:
             "loss": loss.item(), "solver": "fp64, rtol 1e-10 forward and transposed"}
 
 
-def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
+def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4, n_sub: int = 1,
+               per_vcycle: bool = True) -> dict:
     """The single-defect run of Sec. 4.4 on its N x N x N/2 grid (h = L/(N/2)):
     chi from Eq. case0_chi, l = h, dt = 200 t_s, U = 1e-7 L/t_s, the sample at
     rest and free of stress at t = 0.  `steps` FP32-IR projection steps
@@ -271,7 +272,7 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
     dev = torch.device("cuda:0")
     nx, ny, nz = N, N, N // 2
     h = 1.0 / nz
-    P, dt, U = dict(stz_constants(), l_diff=h), 200.0, 1e-7
+    P, dt, U = dict(stz_constants(), l_diff=h, n_sub=n_sub), 200.0, 1e-7
     st = defect_state(nx, ny, nz, U)
     g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=min_coarse_nz, precision="fp32-ir",
                  device=dev)
@@ -289,6 +290,9 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
         if (i + 1) % 500 == 0 or i + 1 == steps:
             torch.cuda.synchronize()
             marks.append(time.perf_counter())
+            if steps > 1500:
+                print("defect run: %d steps, %.1f s" % (i + 1, marks[-1] - t0), file=sys.stderr,
+                      flush=True)
     ms = (marks[-1] - t0) * 1e3 / steps
     phases = []
     for m in range(len(marks) - 1):
@@ -304,6 +308,22 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
     levels = g.levels
     g.close()
     del v0, s0, c0, v, s, c, sbar, p_
+    res = {"grid": [nx, ny, nz], "levels": levels, "min_coarse_nz": min_coarse_nz,
+           "steps": steps, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
+           "vcycles": sum(cycles), "vcycles_per_step": sum(cycles) / steps,
+           "max_vcycles_in_a_step": max(cycles), "phases": phases, "state_at_end": state,
+           "plastic_substeps": ("single step (Eq. sig_star_qs)" if n_sub == 1 else
+                                "per cell from the stability bound" if n_sub == -1 else n_sub),
+           "solver": "fp32-ir, rtol 1e-10",
+           "inputs": "chi Eq. case0_chi (550 K + 170 K Gaussian), sigma = 0, v = 0 at t = 0; "
+                     "l = h, dt = 200 t_s, U = 1e-7 L/t_s",
+           "paper_context_32_cpu_processes": {
+               "s_per_vcycle_table3": 0.76, "s_per_vcycle_table2": 0.55,
+               "single_defect_run": {"steps": 5000, "hours": 7.52, "vcycle_hours": 5.852,
+                                     "vcycles": 17586}}}
+    if not per_vcycle:
+        torch.cuda.empty_cache()
+        return res
     sig = stress_field_device(nx, ny, nz, 2, dev)
     gr = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=min_coarse_nz, precision="fp64",
                   device=dev)
@@ -329,17 +349,8 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4) -> dict:
         gs.close()
     del b, x
     torch.cuda.empty_cache()
-    return {"grid": [nx, ny, nz], "levels": levels, "min_coarse_nz": min_coarse_nz,
-            "steps": steps, "ms_per_step": ms, "steps_per_s": 1e3 / ms,
-            "vcycles": sum(cycles), "vcycles_per_step": sum(cycles) / steps,
-            "max_vcycles_in_a_step": max(cycles), "phases": phases, "state_at_end": state,
-            "solver": "fp32-ir, rtol 1e-10", "per_vcycle_from_zero": per_cycle,
-            "inputs": "chi Eq. case0_chi (550 K + 170 K Gaussian), sigma = 0, v = 0 at t = 0; "
-                      "l = h, dt = 200 t_s, U = 1e-7 L/t_s",
-            "paper_context_32_cpu_processes": {
-                "s_per_vcycle_table3": 0.76, "s_per_vcycle_table2": 0.55,
-                "single_defect_run": {"steps": 5000, "hours": 7.52, "vcycle_hours": 5.852,
-                                      "vcycles": 17586}}}
+    res["per_vcycle_from_zero"] = per_cycle
+    return res
 
 
 def weld_run(N: int = 256, steps: int = 100, both: bool = True) -> dict:

@@ -105,6 +105,9 @@ typedef struct {
   double l_diff;           /* diffusion length l of Eq. chi_evo (units of L);
                               0 leaves the diffusion term out; the reverse-mode
                               entry points require 0                          */
+  int n_sub;               /* sub-steps of the plastic terms (qs_stz_step);
+                              0 or 1: the single step of Eq. sig_star_qs; the
+                              reverse-mode entry points require 0 or 1        */
 } qs_stz_params;
 
 typedef struct qs_handle qs_handle;
@@ -157,6 +160,16 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol,
  * layer holds the linear extrapolation of sigma and chi from the two nearest
  * layers (Sec. 3.5), with D^pl evaluated on it (0 where the extrapolated chi
  * is not positive).  D^pl, sbar and chi are those of step n.
+ * Sub-steps (an extension; the paper takes the single step above): with
+ * n_sub = M > 1, or n_sub = -1 and M = ceil(4 mu dt dD^pl/dsbar) at the state
+ * of step n clamped to [1, 65536] per cell, the plastic terms take M forward-
+ * Euler steps of dt/M, each from the state the previous one left:
+ *   sigma_{m+1} = sigma_m - (dt/M) 2 mu (D^pl/sbar)(sigma_m) sigma_{0,m},
+ *   chi_{m+1}   = chi_m + (dt/M)/c0 (2 sbar_m D^pl_m / s_y) (chi_inf - chi_m),
+ * then sigma* = sigma_M + dt (L sigma + sigma L^T - tr(L) sigma) with sigma
+ * of step n, and chi' = chi_M + the diffusion term above.  For n_sub = -1 each
+ * sub-step keeps (dt/M) 2 mu dD^pl/dsbar <= 1/2 at the start state, below the
+ * explicit step's stability limit of 2.  Other n_sub < -1: QS_ERR_ARG.
  * Outputs may not alias inputs. */
 qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v,
                       const double* sigma, const double* chi, double* sigma_star,
@@ -199,7 +212,7 @@ qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp,
  *                        `scratch`: device memory of qs_step_scratch_bytes().
  *                        At sbar == s_y the one-sided derivative of the
  *                        elastic branch (D^pl = 0) is used.  Refuses l > 0
- *                        (QS_ERR_ARG) and grids with 9 nz ny nx >= 2^31
+ *                        or n_sub outside {0, 1} (QS_ERR_ARG) and grids with 9 nz ny nx >= 2^31
  *                        (QS_ERR_SHAPE: the gradient cotangent is indexed
  *                        with 32-bit integers as [9][cells]).
  *  qs_rhs_vjp:           g_sstar += D_h^T g_b / dt (g_b interior nodes).

@@ -678,7 +678,7 @@ namespace {
 
 bool valid_stz(const qs_stz_params* sp) {
   return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt) &&
-         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff);
+         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff) && sp->n_sub >= -1;
 }
 
 StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
@@ -694,6 +694,7 @@ StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
   a.mu = hd->p.mu;
   a.h = hd->p.h;
   a.l2 = sp->l_diff * sp->l_diff;
+  a.n_sub = sp->n_sub <= 1 && sp->n_sub >= 0 ? 1 : sp->n_sub;
   return a;
 }
 
@@ -808,7 +809,7 @@ qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* 
                           const double* g_chi1, double* g_sigma, double* g_chi, double* g_v,
                           void* scratch) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !g_sstar || !g_chi1 || !g_sigma || !g_chi ||
-      !g_v || !scratch || sp->l_diff != 0.0)
+      !g_v || !scratch || sp->l_diff != 0.0 || sp->n_sub > 1 || sp->n_sub < 0)
     return QS_ERR_ARG;
   const Dims d = hd->L[0].d;
   // the velocity-gradient cotangent is stored as [9][cells] with 32-bit indices

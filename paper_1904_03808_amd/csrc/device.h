@@ -142,6 +142,7 @@ struct StzArgs {
   double s_y, tau0, beta, delta_over_T, c0, chi_inf, dt;
   double lam, mu, h;
   double l2;  // squared diffusion length of Eq. chi_evo (0: no diffusion term)
+  int n_sub;  // plastic sub-steps: 1 single step, > 1 fixed count, -1 per cell
 };
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
                      double* chi1, Dims d, const StzArgs& a, hipStream_t s);

@@ -87,6 +87,15 @@ __device__ __forceinline__ Plastic plastic_rate(double sbar, double chi, const S
   return p;
 }
 
+// D^pl alone (Eq. stz_dpl), for the sub-step loop.
+__device__ __forceinline__ double plastic_D(double sbar, double chi, const StzArgs& a) {
+  if (!(sbar > a.s_y)) return 0.0;
+  const double A = exp(-1.0 / chi) * exp(-a.delta_over_T) / a.tau0;
+  return A * cosh(a.beta * sbar) * (1.0 - a.s_y / sbar);
+}
+
+constexpr int kMaxSubsteps = 65536;
+
 __device__ __forceinline__ void deviator(const double S[3][3], double S0[3][3], double* sbar) {
   const double pr = (S[0][0] + S[1][1] + S[2][2]) * (1.0 / 3.0);
   double q = 0.0;
@@ -185,22 +194,61 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
   deviator(S, S0, &sbar);
   const double x = chi[t];
   const Plastic pl = plastic_rate(sbar, x, a);
-  const double rho = pl.D > 0.0 ? pl.D / sbar : 0.0;
   const double trL = L[0][0] + L[1][1] + L[2][2];
-  // C : (rho S0) = lambda tr(rho S0) I + 2 mu rho S0, and tr(S0) = 0
+  double xn;
+  if (a.n_sub == 1) {
+    const double rho = pl.D > 0.0 ? pl.D / sbar : 0.0;
+    // C : (rho S0) = lambda tr(rho S0) I + 2 mu rho S0, and tr(S0) = 0
 #pragma unroll
-  for (int n = 0; n < 6; ++n) {
-    const int p = VA[n], q = VB[n];
-    double LS = 0.0, SLt = 0.0;
+    for (int n = 0; n < 6; ++n) {
+      const int p = VA[n], q = VB[n];
+      double LS = 0.0, SLt = 0.0;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      LS += L[p][m] * S[m][q];
-      SLt += S[p][m] * L[q][m];
+      for (int m = 0; m < 3; ++m) {
+        LS += L[p][m] * S[m][q];
+        SLt += S[p][m] * L[q][m];
+      }
+      const double rate = LS + SLt - trL * S[p][q] - 2.0 * a.mu * rho * S0[p][q];
+      sstar[n * N + t] = S[p][q] + a.dt * rate;
     }
-    const double rate = LS + SLt - trL * S[p][q] - 2.0 * a.mu * rho * S0[p][q];
-    sstar[n * N + t] = S[p][q] + a.dt * rate;
+    xn = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
+  } else {
+    // sub-steps of the plastic terms from the state of step n
+    int M = a.n_sub;
+    if (M < 0) {
+      const double m = ceil(4.0 * a.mu * a.dt * pl.dD_ds);
+      M = !(m < static_cast<double>(kMaxSubsteps)) ? kMaxSubsteps : (m < 1.0 ? 1 : static_cast<int>(m));
+    }
+    const double tau = a.dt / M;
+    double Sp[3][3], xp = x;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Sp[p][q] = S[p][q];
+    for (int it = 0; it < M; ++it) {
+      double P0[3][3], sb;
+      deviator(Sp, P0, &sb);
+      const double D = plastic_D(sb, xp, a);
+      const double r = D > 0.0 ? D / sb : 0.0;
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Sp[p][q] = Sp[p][q] - tau * (2.0 * a.mu * r * P0[p][q]);
+      xp = xp + (tau / a.c0) * (2.0 * sb * D / a.s_y) * (a.chi_inf - xp);
+    }
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      const int p = VA[n], q = VB[n];
+      double LS = 0.0, SLt = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        LS += L[p][m] * S[m][q];
+        SLt += S[p][m] * L[q][m];
+      }
+      sstar[n * N + t] = Sp[p][q] + a.dt * (LS + SLt - trL * S[p][q]);
+    }
+    xn = xp;
   }
-  double xn = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
   if (DIFF) {
     // the cell's own D^pl as in the flux form (0 where chi is not positive)
     const double Dc = x > 0.0 ? pl.D : 0.0;

@@ -98,6 +98,42 @@ def test_stz_step_with_chi_diffusion(n):
         assert np.abs(term).max() * (dt / P["c0"]) * l * l > 0.05 * np.abs(rc - chi).max()
 
 
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20)])
+@pytest.mark.parametrize("n_sub,dt", [(4, 10.0), (-1, 10.0), (-1, 40.0)])
+def test_stz_step_with_plastic_substeps(n, n_sub, dt):
+    """Sub-stepped plastic terms, a fixed count and the per-cell count from
+    the stability bound (up to about 40 and 150 sub-steps in these states),
+    match the oracle's."""
+    rng = np.random.default_rng(4)
+    nx, ny, nz = n
+    h = 1.0 / nz
+    g = solver(nx, ny, nz)
+    v, sig, chi = random_state(rng, nx, ny, nz)
+    p = dict(P, n_sub=n_sub)
+    ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
+    rs, rc = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
+    assert rel(host(ss), rs) < 1e-12
+    assert rel(host(c1) - chi, rc - chi) < 1e-11
+    # the sub-steps change the result where cells are stiff
+    r1, _ = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, dict(p, n_sub=1))
+    assert rel(rs, r1) > 1e-6
+
+
+def test_substep_arguments():
+    """n_sub below -1 is refused, and so is any n_sub > 1 in reverse mode."""
+    from paper_1904_03808_amd._capi import QSError
+    nx, ny, nz = 8, 8, 8
+    rng = np.random.default_rng(2)
+    g = solver(nx, ny, nz)
+    v, sig, chi = random_state(rng, nx, ny, nz)
+    with pytest.raises(QSError):
+        g.stz_step(dict(P, n_sub=-2), 1.0, dev(v), dev(sig), dev(chi))
+    z = lambda *s: torch.zeros(s, dtype=torch.float64, device="cuda")
+    with pytest.raises(QSError):
+        g.stz_step_vjp(dict(P, n_sub=2), 1.0, dev(v), dev(sig), dev(chi), z(6, nz, ny, nx),
+                       z(nz, ny, nx), z(3, nz + 1, ny, nx))
+
+
 def test_reverse_mode_refuses_chi_diffusion():
     """The reverse-mode STZ step is written for l = 0 and refuses l > 0."""
     from paper_1904_03808_amd._capi import QSError
@@ -144,8 +180,8 @@ def test_projection_steps(prec):
         assert rel(host(cd), chi) < 1e-13, step
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
-def test_projection_steps_single_defect(prec):
+@pytest.mark.parametrize("prec,n_sub", [("fp64", 1), ("fp32-ir", 1), ("fp32-ir", -1)])
+def test_projection_steps_single_defect(prec, n_sub):
     """Three steps of the single-defect run (Sec. 4.4: chi from Eq. case0_chi,
     l = h, dt = 200 t_s, U = 1e-7 L/t_s) on its N x N x N/2 shape at N = 32,
     with three multigrid levels down to 8 x 8 x 4.  The sample is preloaded with sigma_xz just above yield, so that the plastic
@@ -153,7 +189,7 @@ def test_projection_steps_single_defect(prec):
     from rest)."""
     nx, ny, nz, dt, U = 32, 32, 16, 200.0, 1e-7
     h = 1.0 / nz
-    p = dict(P, l_diff=h)
+    p = dict(P, l_diff=h, n_sub=n_sub)
     st = defect_state(nx, ny, nz, U)
     v, sig, chi = st["v"], st["sigma"], st["chi"]
     sig[4] = 1.01 * P["s_y"]
