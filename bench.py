@@ -251,16 +251,18 @@ def config4_adjoint(n: int = 96, steps: int = 10) -> dict:
             "loss": loss.item(), "solver": "fp64, rtol 1e-10 forward and transposed"}
 
 
-def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4, n_sub: int = 1,
+def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: int = -1,
                per_vcycle: bool = True) -> dict:
     """The single-defect run of Sec. 4.4 on its N x N x N/2 grid (h = L/(N/2)):
     chi from Eq. case0_chi, l = h, dt = 200 t_s, U = 1e-7 L/t_s, the sample at
     rest and free of stress at t = 0.  `steps` FP32-IR projection steps
     (rtol 1e-10, warm-started) are timed between device synchronisations, with
     a split every 500 steps: elastic loading (to t = 1e5 t_s), yield, then
-    plastic flow concentrating in the defect.  1500 steps stay below the point
-    (t near 3.7e5 t_s) where the single forward-Euler step of the plastic
-    term loses stability in the defect.  Then the time per V-cycle at this
+    plastic flow concentrating in the defect and a band forming.  The default
+    is the paper's whole run (5000 steps to t = 1e6 t_s) with the plastic terms
+    sub-stepped per cell (n_sub = -1): with the single forward-Euler step of
+    Eq. sig_star_qs (n_sub = 1) the run loses stability near t = 3.7e5 t_s,
+    so at most about 1850 steps can be run that way.  Then the time per V-cycle at this
     shape, FP32-IR and FP64, from solves from zero of a D_h sigma right-hand
     side (seed 2): the figure the paper tabulates (Tables 2 and 3, and the
     single-defect run's V-cycle total)."""
@@ -353,13 +355,18 @@ def defect_run(N: int = 256, steps: int = 1500, min_coarse_nz: int = 4, n_sub: i
     return res
 
 
-def weld_run(N: int = 256, steps: int = 100, both: bool = True) -> dict:
+def weld_run(N: int = 256, steps: int = 12, both: bool = True) -> dict:
     """Friction welding (Sec. 5) on the slender N x N x N/4 sample (h = 2L/N):
     spinning-disc wall data of Eqs. u_weld and v_weld on both walls
     (omega = 2 pi / 1e8 t_s, R = 1/3), chi from Eq. convolve with mean 450 K,
     std 15 K, l_c = 5h, l = h, dt = 2e4 t_s, the sample at rest at t = 0.
     `steps` FP32-IR projection steps (rtol 1e-10, warm-started) timed between
-    device synchronisations."""
+    device synchronisations, the plastic terms sub-stepped per cell.  The
+    default 12 steps cover the elastic loading and the onset of yield (sbar
+    reaches 2 s_Y near the disc edges).  Later steps leave the explicit
+    scheme's reach at this dt: near step 15 the chi diffusion number
+    (dt/c0) 6 D^pl l^2/h^2 passes 1, and without diffusion the local
+    relaxation near step 38 needs more than 65536 sub-steps."""
     import math
 
     import torch
@@ -370,7 +377,7 @@ def weld_run(N: int = 256, steps: int = 100, both: bool = True) -> dict:
     dev = torch.device("cuda:0")
     nx, ny, nz = N, N, N // 4
     h = 2.0 / N
-    P, dt, omega = dict(stz_constants(), l_diff=h), 2e4, 2 * math.pi / 1e8
+    P, dt, omega = dict(stz_constants(), l_diff=h, n_sub=-1), 2e4, 2 * math.pi / 1e8
     lo, hi = (torch.from_numpy(w).to(dev) for w in weld_walls(nx, ny, nz, omega, h, True, both))
     c0 = torch.from_numpy(chi_field(nx, ny, nz, 5, 450.0 / 21000, 15.0 / 21000, 5.0)).to(dev)
     g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=4, precision="fp32-ir", device=dev)
@@ -393,7 +400,7 @@ def weld_run(N: int = 256, steps: int = 100, both: bool = True) -> dict:
            "max_vcycles_in_a_step": max(cycles), "walls": "both" if both else "top",
            "state_at_end": {"t_end": steps * dt,
                             "sbar_max_over_sY": (sbar.max() / P["s_y"]).item()},
-           "solver": "fp32-ir, rtol 1e-10",
+           "solver": "fp32-ir, rtol 1e-10", "plastic_substeps": "per cell from the stability bound",
            "inputs": "chi Eq. convolve (450 K, 15 K, l_c = 5h, seed 5), sigma = 0, v = 0 at t = 0; "
                      "l = h, dt = 2e4 t_s, omega = 2 pi / 1e8 t_s, R = 1/3"}
     g.close()
@@ -514,9 +521,8 @@ def main():
                     help="skip the shear-step (256^3) and adjoint (96^3) blocks")
     ap.add_argument("--no-defect", action="store_true",
                     help="skip the single-defect (256 x 256 x 128) and welding (256 x 256 x 64) blocks")
-    ap.add_argument("--defect-steps", type=int, default=1500,
-                    help="projection steps of the single-defect block (the paper's run has 5000; "
-                         "beyond about 1850 the forward-Euler plastic step is unstable)")
+    ap.add_argument("--defect-steps", type=int, default=5000,
+                    help="projection steps of the single-defect block (the paper's whole run)")
     ap.add_argument("--defect-only", action="store_true",
                     help="only run the single-defect and welding blocks and print them")
     ap.add_argument("--no-table3", action="store_true",
