@@ -77,7 +77,7 @@ struct SweepArgs {
 constexpr int kPad = 2;  // LDS row: [unused][copy of col nx-1][cols 0..nx-1][copy of col 0][unused]
 
 // rows of one parity per workgroup: two at 256 columns, more for shorter rows
-// (at most 256 threads), one at 512
+// (at most 256 threads), one at 384, 512 and 768 (384 threads)
 int rows_per_group(int nx) { return std::max(1, std::min(64, 512 / nx)); }
 
 // Per-thread state of the sweep, passed by value so that it stays in registers.
@@ -297,8 +297,11 @@ __device__ __forceinline__ void march_step(const Ctx<T, NX>& c, const T* __restr
   __syncthreads();
 }
 
+// threads per workgroup: rows * nx/2, at most 256 except for 768-column rows
+constexpr int sweep_max_threads(int nx) { return nx == 768 ? 384 : 256; }
+
 template <typename T, int NX, int X1, int Z>
-__global__ __launch_bounds__(256) void k_sweep_rows(const T* __restrict__ own_src,
+__global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* __restrict__ own_src,
                                                     const T* __restrict__ nbr_src,
                                                     T* __restrict__ dst, const T* __restrict__ b,
                                                     SweepArgs a, FineCoef<T> cf) {
@@ -416,7 +419,9 @@ void set_lds_limit_all(int bytes) {
   set_lds_limit_one<T, 0>(bytes);
   set_lds_limit_one<T, 128>(bytes);
   set_lds_limit_one<T, 256>(bytes);
+  set_lds_limit_one<T, 384>(bytes);
   set_lds_limit_one<T, 512>(bytes);
+  set_lds_limit_one<T, 768>(bytes);
 }
 
 }  // namespace
@@ -430,7 +435,9 @@ int blocks_per_cu(Dims d, int threads, size_t lds) {
   switch (d.nx) {
     case 128: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 128, 0, 0>); break;
     case 256: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 256, 0, 0>); break;
+    case 384: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 384, 0, 0>); break;
     case 512: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 512, 0, 0>); break;
+    case 768: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 768, 0, 0>); break;
     default: k = reinterpret_cast<const void*>(&k_sweep_rows<T, 0, 0, 0>); break;
   }
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) n = 1;
@@ -451,7 +458,16 @@ int sweep_segment_length(Dims d, int bytes_per_value) {
   const int per_cu = bytes_per_value == 8 ? blocks_per_cu<double>(d, threads, lds)
                                           : blocks_per_cu<float>(d, threads, lds);
   const int groups = std::max(1, ((d.ny + 1) / 2 + R - 1) / R);
-  const int nseg = std::max(1, (per_cu * cus) / groups);
+  const int slots = per_cu * cus;
+  int nseg = std::max(1, slots / groups);
+  // more row groups than resident slots: split z so that the launch is a
+  // whole number of rounds when two or four segments make it one
+  if (groups > slots && groups % slots != 0)
+    for (int k : {2, 4})
+      if ((groups * k) % slots == 0) {
+        nseg = k;
+        break;
+      }
   const int seg = (d.nz - 1 + nseg - 1) / nseg;
   return std::max(seg, 4);
 }
@@ -461,7 +477,8 @@ int sweep_lds_bytes(Dims d, int bytes_per_value) {
 }
 
 bool sweep_supported(Dims d, size_t lds_limit, int bytes_per_value) {
-  if (d.nx % 2 != 0 || d.ny % 2 != 0 || d.nx < 4 || d.nx > 512 || d.nz < 2) return false;
+  if (d.nx % 2 != 0 || d.ny % 2 != 0 || d.nx < 4 || d.nz < 2) return false;
+  if (d.nx > 512 && d.nx != 768) return false;
   return static_cast<size_t>(sweep_lds_bytes(d, bytes_per_value)) <= lds_limit;
 }
 
@@ -489,7 +506,9 @@ void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, D
   switch (d.nx) {
     case 128: launch_nx<T, 128>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
     case 256: launch_nx<T, 256>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
+    case 384: launch_nx<T, 384>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
     case 512: launch_nx<T, 512>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
+    case 768: launch_nx<T, 768>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
     default: launch_nx<T, 0>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
   }
 }

@@ -210,11 +210,12 @@ def test_fp32_refinement(n):
 
 @pytest.mark.parametrize("n,mc", [((32, 32, 32), 4), ((40, 24, 32), 4), ((16, 16, 64), 16),
                                   ((256, 16, 16), 4), ((512, 16, 16), 4), ((128, 10, 8), 4),
-                                  ((8, 8, 16), 8)])
+                                  ((8, 8, 16), 8), ((384, 24, 16), 4), ((768, 16, 32), 4)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
 def test_row_sweep_matches_oracle(n, mc, prec):
     """The row-parity sweep kernel (ping-pong, z-segments, halo recomputation,
-    row lengths with and without a specialised kernel, last row groups that
+    row lengths with and without a specialised kernel (384 and 768 columns
+    with one row per workgroup, 768 with 384 threads), last row groups that
     repeat a row: 16 x 16, 128 x 10, and 8 x 8, where one group of 64 rows
     holds the 4 rows of a parity) equals the oracle's colour-by-colour
     Gauss-Seidel sweep on every smoothed level, for 1 and 3 sweeps."""
