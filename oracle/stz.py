@@ -85,6 +85,61 @@ def flux_divergence(D, chi, h):
     return out / (h * h)
 
 
+def z_ghosts2(f):
+    """f [..., nz, ny, nx] extended by two cell layers below and above in z,
+    the linear continuation of the two nearest layers (Sec. 3.5)."""
+    d0 = f[..., 1:2, :, :] - f[..., :1, :, :]
+    d1 = f[..., -1:, :, :] - f[..., -2:-1, :, :]
+    lo = [f[..., :1, :, :] - 2.0 * d0, f[..., :1, :, :] - d0]
+    hi = [f[..., -1:, :, :] + d1, f[..., -1:, :, :] + 2.0 * d1]
+    return np.concatenate(lo + [f] + hi, axis=-3)
+
+
+def eno_derivative(g, u, h, axis):
+    """Eq. ENO along `axis` of the ghosted array g, whose cells 2 .. n+1 along
+    that axis are the interior (two extra cells each side); u is the velocity
+    component along the axis at the interior cells.  Upwinded second-order
+    one-sided difference where the curvature on the upwind side is smaller,
+    the centred difference otherwise."""
+    n = g.shape[axis] - 4
+
+    def at(o):  # values at interior offset o (-2 .. 2)
+        return np.take(g, np.arange(2 + o, 2 + o + n), axis=axis)
+
+    fm2, fm1, f0, fp1, fp2 = at(-2), at(-1), at(0), at(1), at(2)
+    cm = np.abs(f0 - 2.0 * fm1 + fm2)   # |f_xx| at i-1, times h^2
+    c0 = np.abs(fp1 - 2.0 * f0 + fm1)   # at i
+    cp = np.abs(fp2 - 2.0 * fp1 + f0)   # at i+1
+    fwd = -fp2 + 4.0 * fp1 - 3.0 * f0
+    bwd = 3.0 * f0 - 4.0 * fm1 + fm2
+    ctr = fp1 - fm1
+    d = np.where((u < 0.0) & (c0 > cp), fwd, np.where((u > 0.0) & (c0 > cm), bwd, ctr))
+    return d / (2.0 * h)
+
+
+def cell_velocity(v):
+    """Velocity at the cell centres: mean of the cell's eight corner nodes."""
+    acc = 0.0
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                acc = acc + np.roll(np.roll(v[:, dz:v.shape[1] - 1 + dz], -dy, axis=2), -dx, axis=3)
+    return acc / 8.0
+
+
+def advection(sigma, v, h):
+    """(v . grad) sigma at the cells (Eq. sig_star_evol), each component of
+    the Voigt stress differentiated by Eq. ENO in x, y and z with the
+    velocity at the cell centre; x and y wrap, z uses two extrapolated ghost
+    layers."""
+    u = cell_velocity(v)
+    gz = z_ghosts2(sigma)
+    gy = np.concatenate([sigma[..., -2:, :], sigma, sigma[..., :2, :]], axis=-2)
+    gx = np.concatenate([sigma[..., -2:], sigma, sigma[..., :2]], axis=-1)
+    return (u[0] * eno_derivative(gx, u[0], h, -1) + u[1] * eno_derivative(gy, u[1], h, -2)
+            + u[2] * eno_derivative(gz, u[2], h, -3))
+
+
 def chi_diffusion(sigma, chi, h, p):
     """div(D^pl grad chi) per cell for the state (sigma, chi) of step n."""
     sg, cg = z_ghosts(sigma), z_ghosts(chi)
@@ -182,9 +237,14 @@ def stz_step(v, sigma, chi, h, dt, lam, mu, p):
     v: node velocity at step n (walls included), sigma: Voigt cell stress,
     chi: cell effective temperature.  Returns (sigma_star, chi_next).  With
     p["l_diff"] = l > 0 the diffusion term l^2 div(D^pl grad chi) joins the
-    chi step.
+    chi step; with p["advect"] true the advection -(v . grad) sigma of
+    Eq. sig_star_evol (the explicit method's Eq. stress_evo_exp carries it too;
+    the quasi-static Eq. sig_star_qs does not) joins sigma*, with v and sigma
+    of step n.
     """
     sstar, chi_next = stz_pointwise(grad_cell(v, h), sigma, chi, dt, lam, mu, p)
+    if p.get("advect", 0):
+        sstar = sstar - dt * advection(sigma, v, h)
     l = p.get("l_diff", 0.0)
     if l > 0.0:
         chi_next = chi_next + (dt / p["c0"]) * (l * l) * chi_diffusion(sigma, chi, h, p)

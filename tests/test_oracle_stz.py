@@ -343,3 +343,69 @@ def test_adaptive_substeps_keep_a_stiff_cell_stable():
     assert a[2] == b[2] == c[2] and a[3] == b[3] == c[3]
     # the single step flips the deviator and leaves it larger than it started
     assert a[2] > 10 * 1.25 * P["s_y"]
+
+
+def test_eno_derivative_branches_by_hand():
+    """Eq. ENO on five values f(i-2 .. i+2) = 0, 0, 0, 1, 4 with h = 1/2 (so
+    the factor 1/(2h) is 1): the curvatures |f_xx| h^2 at i-1, i, i+1 are
+    0, 1, 2.  Moving right (u > 0), i is more curved than i-1: the backward
+    three-point formula gives 3*0 - 4*0 + 0 = 0.  Moving left, i is less
+    curved than i+1: the centred difference 1 - 0 = 1.  At rest: centred."""
+    g = np.array([0.0, 0.0, 0.0, 1.0, 4.0])
+    for u, want in ((1.0, 0.0), (-1.0, 1.0), (0.0, 1.0)):
+        d = stz.eno_derivative(g, np.array([u]), 0.5, 0)
+        assert d.shape == (1,) and d[0] == want
+    # mirrored values: moving left now takes the forward formula
+    g = np.array([4.0, 1.0, 0.0, 0.0, 0.0])
+    assert stz.eno_derivative(g, np.array([-1.0]), 0.5, 0)[0] == -(-0.0 + 4 * 0.0 - 3 * 0.0)
+    assert stz.eno_derivative(g, np.array([1.0]), 0.5, 0)[0] == 0.0 - 1.0
+    # every branch is exact for a quadratic
+    x = np.arange(-2, 9) * 0.1
+    f = 0.3 - 1.7 * x + 2.5 * x * x
+    for u in (-1.0, 0.0, 1.0):
+        d = stz.eno_derivative(f, np.full(7, u), 0.1, 0)
+        assert np.allclose(d, -1.7 + 5.0 * x[2:-2], rtol=0, atol=1e-12)
+
+
+def test_advection_of_a_field_linear_in_z_is_exact():
+    """sigma = a + b z (every component its own a, b) is continued exactly by
+    the linear ghost layers, so (v . grad) sigma = w_cell b at every cell,
+    including those next to the walls, for any velocity; w_cell is the mean
+    of the cell's eight corners."""
+    rng = np.random.default_rng(13)
+    nx, ny, nz = 6, 5, 4
+    h = 0.25
+    zc = (np.arange(nz) + 0.5) * h
+    a, b = rng.standard_normal(6), rng.standard_normal(6)
+    sigma = np.broadcast_to((a[:, None] + b[:, None] * zc)[:, :, None, None],
+                            (6, nz, ny, nx)).copy()
+    v = rng.standard_normal((3, nz + 1, ny, nx))
+    adv = stz.advection(sigma, v, h)
+    w = np.zeros((nz, ny, nx))
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w += v[2, dz:nz + dz][:, (np.arange(ny) + dy) % ny][:, :, (np.arange(nx) + dx) % nx]
+    w /= 8.0
+    assert np.allclose(adv, b[:, None, None, None] * w, rtol=1e-12, atol=1e-13)
+
+
+def test_advection_is_second_order_for_smooth_fields():
+    """A smooth periodic-in-x,y field advected by a uniform velocity: the
+    error against the exact u . grad sigma at cells at least two layers from
+    the walls falls by about 4 when h halves."""
+    U = np.array([0.7, -0.4, 0.3])
+    errs = []
+    for n in (16, 32):
+        h = 1.0 / n
+        xc = (np.arange(n) + 0.5) * h
+        Z, Y, X = np.meshgrid(xc, xc, xc, indexing="ij")
+        f = np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) * (1 + Z * Z)
+        df = (U[0] * 2 * np.pi * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Y) * (1 + Z * Z)
+              - U[1] * 2 * np.pi * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y) * (1 + Z * Z)
+              + U[2] * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y) * 2 * Z)
+        sigma = np.broadcast_to(f, (6, n, n, n)).copy()
+        v = np.broadcast_to(U[:, None, None, None], (3, n + 1, n, n)).copy()
+        adv = stz.advection(sigma, v, h)
+        errs.append(np.abs(adv[:, 2:-2] - df[2:-2]).max())
+    assert 3.3 < errs[0] / errs[1] < 4.7, errs
