@@ -108,6 +108,9 @@ typedef struct {
   int n_sub;               /* sub-steps of the plastic terms (qs_stz_step);
                               0 or 1: the single step of Eq. sig_star_qs; the
                               reverse-mode entry points require 0 or 1        */
+  int advect;              /* 0 (Eq. sig_star_qs) or 1: sigma* also carries
+                              -dt (v . grad) sigma (qs_stz_step); the reverse-
+                              mode entry points require 0                     */
 } qs_stz_params;
 
 typedef struct qs_handle qs_handle;
@@ -170,6 +173,14 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol,
  * of step n, and chi' = chi_M + the diffusion term above.  For n_sub = -1 each
  * sub-step keeps (dt/M) 2 mu dD^pl/dsbar <= 1/2 at the start state, below the
  * explicit step's stability limit of 2.  Other n_sub < -1: QS_ERR_ARG.
+ * Advection (advect = 1; the stress equation of Eq. sig_star_evol carries it,
+ * the quasi-static Eq. sig_star_qs leaves it out): sigma* -= dt (u . grad)
+ * sigma with sigma and v of step n, u the mean of the cell's eight corner
+ * velocities, and each derivative by Eq. ENO along its axis (upwind
+ * three-point formula where the cell is more curved than its upwind
+ * neighbour, centred difference otherwise); x and y wrap, and in z two ghost
+ * layers continue the two nearest layers linearly (Sec. 3.5).  l > 0 or
+ * advect = 1 need nz >= 2 (else QS_ERR_SHAPE).
  * Outputs may not alias inputs. */
 qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v,
                       const double* sigma, const double* chi, double* sigma_star,
@@ -211,8 +222,8 @@ qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp,
  *                        cotangent into g_v (node vector; walls untouched);
  *                        `scratch`: device memory of qs_step_scratch_bytes().
  *                        At sbar == s_y the one-sided derivative of the
- *                        elastic branch (D^pl = 0) is used.  Refuses l > 0
- *                        or n_sub outside {0, 1} (QS_ERR_ARG) and grids with 9 nz ny nx >= 2^31
+ *                        elastic branch (D^pl = 0) is used.  Refuses l > 0,
+ *                        n_sub outside {0, 1} or advect (QS_ERR_ARG) and grids with 9 nz ny nx >= 2^31
  *                        (QS_ERR_SHAPE: the gradient cotangent is indexed
  *                        with 32-bit integers as [9][cells]).
  *  qs_rhs_vjp:           g_sstar += D_h^T g_b / dt (g_b interior nodes).

@@ -678,7 +678,8 @@ namespace {
 
 bool valid_stz(const qs_stz_params* sp) {
   return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt) &&
-         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff) && sp->n_sub >= -1;
+         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff) && sp->n_sub >= -1 &&
+         (sp->advect == 0 || sp->advect == 1);
 }
 
 StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
@@ -695,6 +696,7 @@ StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
   a.h = hd->p.h;
   a.l2 = sp->l_diff * sp->l_diff;
   a.n_sub = sp->n_sub <= 1 && sp->n_sub >= 0 ? 1 : sp->n_sub;
+  a.advect = sp->advect;
   return a;
 }
 
@@ -715,7 +717,7 @@ qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v, c
                       const double* chi, double* sigma_star, double* chi_next) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !sigma_star || !chi_next) return QS_ERR_ARG;
   if (sigma_star == sigma || chi_next == chi) return QS_ERR_ARG;
-  if (sp->l_diff > 0.0 && hd->L[0].d.nz < 2) return QS_ERR_SHAPE;  // ghost layers need two cells
+  if ((sp->l_diff > 0.0 || sp->advect) && hd->L[0].d.nz < 2) return QS_ERR_SHAPE;  // ghost layers need two cells
   launch_stz_step(v, sigma, chi, sigma_star, chi_next, hd->L[0].d, stz_args(hd, sp), hd->stream);
   return launch_check();
 }
@@ -753,7 +755,7 @@ qs_status projection_step_impl(qs_handle* hd, const qs_stz_params* sp, double U_
     return QS_ERR_ARG;
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
   const Dims d = hd->L[0].d;
-  if (sp->l_diff > 0.0 && d.nz < 2) return QS_ERR_SHAPE;
+  if ((sp->l_diff > 0.0 || sp->advect) && d.nz < 2) return QS_ERR_SHAPE;
   Carver cv{static_cast<char*>(scratch)};
   double* sstar = cv.take<double>(6 * cells(d));
   double* chi1 = cv.take<double>(cells(d));
@@ -809,7 +811,7 @@ qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* 
                           const double* g_chi1, double* g_sigma, double* g_chi, double* g_v,
                           void* scratch) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !g_sstar || !g_chi1 || !g_sigma || !g_chi ||
-      !g_v || !scratch || sp->l_diff != 0.0 || sp->n_sub > 1 || sp->n_sub < 0)
+      !g_v || !scratch || sp->l_diff != 0.0 || sp->n_sub > 1 || sp->n_sub < 0 || sp->advect)
     return QS_ERR_ARG;
   const Dims d = hd->L[0].d;
   // the velocity-gradient cotangent is stored as [9][cells] with 32-bit indices

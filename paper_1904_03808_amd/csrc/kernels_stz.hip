@@ -87,6 +87,71 @@ __device__ __forceinline__ Plastic plastic_rate(double sbar, double chi, const S
   return p;
 }
 
+// Velocity at the cell centre: the mean of the cell's eight corner nodes.
+__device__ __forceinline__ void cell_velocity(const double* __restrict__ v, int nx, int ny, int nz,
+                                              const CellIdx& c, double u[3]) {
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int xs[2] = {c.i, c.ip}, ys[2] = {c.j, c.jp};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double acc = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) acc += v[a * C + (c.k + dz) * P + ys[dy] * nx + xs[dx]];
+    u[a] = acc / 8.0;
+  }
+}
+
+// Eq. ENO from the five values f(-2..2) along one axis and the velocity u
+// along it: the upwind three-point formula where the point is more curved
+// than its upwind neighbour, the centred difference otherwise (times 2h).
+__device__ __forceinline__ double eno_2h(double fm2, double fm1, double f0, double fp1, double fp2,
+                                         double u) {
+#pragma clang fp contract(off)
+  const double cm = fabs(f0 - 2.0 * fm1 + fm2);
+  const double c0 = fabs(fp1 - 2.0 * f0 + fm1);
+  const double cp = fabs(fp2 - 2.0 * fp1 + f0);
+  if (u < 0.0 && c0 > cp) return -fp2 + 4.0 * fp1 - 3.0 * f0;
+  if (u > 0.0 && c0 > cm) return 3.0 * f0 - 4.0 * fm1 + fm2;
+  return fp1 - fm1;
+}
+
+// (u . grad) f at cell t for one cell field f (Eq. sig_star_evol's advection
+// with Eq. ENO per axis): x and y wrap; in z, layers past the walls continue
+// the two nearest layers linearly.
+__device__ __forceinline__ double eno_advection(const double* __restrict__ f, int nx, int ny, int nz,
+                                                const CellIdx& c, int t, const double u[3],
+                                                double h) {
+#pragma clang fp contract(off)
+  const int P = nx * ny;
+  double g[5];
+  // x
+#pragma unroll
+  for (int o = -2; o <= 2; ++o) g[o + 2] = f[t - c.i + (c.i + o + 2 * nx) % nx];
+  const double dx = eno_2h(g[0], g[1], g[2], g[3], g[4], u[0]);
+  // y
+#pragma unroll
+  for (int o = -2; o <= 2; ++o) g[o + 2] = f[t + ((c.j + o + 2 * ny) % ny - c.j) * nx];
+  const double dy = eno_2h(g[0], g[1], g[2], g[3], g[4], u[1]);
+  // z, with the ghost layers
+  const int col = t - c.k * P;
+  const double b0 = f[col], b1 = f[col + P];
+  const double t1 = f[col + (nz - 1) * P], t0 = f[col + (nz - 2) * P];
+  const double d0 = b1 - b0, d1 = t1 - t0;
+#pragma unroll
+  for (int o = -2; o <= 2; ++o) {
+    const int e = c.k + o;
+    g[o + 2] = e < 0 ? (e == -1 ? b0 - d0 : b0 - 2.0 * d0)
+                     : (e > nz - 1 ? (e == nz ? t1 + d1 : t1 + 2.0 * d1) : f[col + e * P]);
+  }
+  const double dz = eno_2h(g[0], g[1], g[2], g[3], g[4], u[2]);
+  const double h2 = 2.0 * h;
+  return u[0] * (dx / h2) + u[1] * (dy / h2) + u[2] * (dz / h2);
+}
+
 // D^pl alone (Eq. stz_dpl), for the sub-step loop.
 __device__ __forceinline__ double plastic_D(double sbar, double chi, const StzArgs& a) {
   if (!(sbar > a.s_y)) return 0.0;
@@ -177,7 +242,7 @@ __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__
 
 // DIFF: with the diffusion term of Eq. chi_evo (l > 0); each cell evaluates
 // D^pl of its six neighbours itself, from sigma and chi of step n.
-template <bool DIFF>
+template <bool DIFF, bool ADV>
 __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
                                                   const double* __restrict__ sigma,
                                                   const double* __restrict__ chi,
@@ -195,6 +260,8 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
   const double x = chi[t];
   const Plastic pl = plastic_rate(sbar, x, a);
   const double trL = L[0][0] + L[1][1] + L[2][2];
+  double u[3] = {0.0, 0.0, 0.0};
+  if (ADV) cell_velocity(v, nx, ny, nz, c, u);
   double xn;
   if (a.n_sub == 1) {
     const double rho = pl.D > 0.0 ? pl.D / sbar : 0.0;
@@ -209,7 +276,9 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
         SLt += S[p][m] * L[q][m];
       }
       const double rate = LS + SLt - trL * S[p][q] - 2.0 * a.mu * rho * S0[p][q];
-      sstar[n * N + t] = S[p][q] + a.dt * rate;
+      double val = S[p][q] + a.dt * rate;
+      if (ADV) val = val - a.dt * eno_advection(sigma + n * N, nx, ny, nz, c, t, u, a.h);
+      sstar[n * N + t] = val;
     }
     xn = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
   } else {
@@ -245,7 +314,9 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
         LS += L[p][m] * S[m][q];
         SLt += S[p][m] * L[q][m];
       }
-      sstar[n * N + t] = Sp[p][q] + a.dt * (LS + SLt - trL * S[p][q]);
+      double val = Sp[p][q] + a.dt * (LS + SLt - trL * S[p][q]);
+      if (ADV) val = val - a.dt * eno_advection(sigma + n * N, nx, ny, nz, c, t, u, a.h);
+      sstar[n * N + t] = val;
     }
     xn = xp;
   }
@@ -596,12 +667,19 @@ inline int blocks_for(long long n, int bs) { return static_cast<int>((n + bs - 1
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
                      double* chi1, Dims d, const StzArgs& a, hipStream_t s) {
   const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
-  if (a.l2 > 0.0)
-    hipLaunchKernelGGL(k_stz_step<true>, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi,
-                       sstar, chi1, d.nx, d.ny, d.nz, a);
+  const dim3 grid(blocks_for(n, 256)), block(256);
+  if (a.l2 > 0.0 && a.advect)
+    hipLaunchKernelGGL((k_stz_step<true, true>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
+                       d.nx, d.ny, d.nz, a);
+  else if (a.l2 > 0.0)
+    hipLaunchKernelGGL((k_stz_step<true, false>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
+                       d.nx, d.ny, d.nz, a);
+  else if (a.advect)
+    hipLaunchKernelGGL((k_stz_step<false, true>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
+                       d.nx, d.ny, d.nz, a);
   else
-    hipLaunchKernelGGL(k_stz_step<false>, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, chi,
-                       sstar, chi1, d.nx, d.ny, d.nz, a);
+    hipLaunchKernelGGL((k_stz_step<false, false>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
+                       d.nx, d.ny, d.nz, a);
 }
 
 void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s) {
