@@ -33,9 +33,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source these counters were taken on.
 SWEEP_COUNTERS = {
     "kernel_source": "paper_1904_03808_amd/csrc/kernels_sweep.hip",
-    "source_sha256_16": "5bae76a0193c3cd7",
+    "source_sha256_16": "27c8e3129c25ec85",
     "n": 256,
-    "fetch_kib": 177897.4,
+    "fetch_kib": 177898.6,
     "write_kib": 97920.0,
     "fetch_scale": 2.0,
     "write_scale": 1.0,
@@ -204,6 +204,8 @@ def config3_shear(n: int = 256, steps: int = 20) -> dict:
     ms = (time.perf_counter() - t0) * 1e3 / steps
     ph = {}
     ph["stz_ms"] = _events_ms(lambda: g.stz_step(P, dt, v, s, c), 3)
+    # the same step with the ENO advection of the stress (not in Eq. sig_star_qs)
+    ph["stz_with_advection_ms"] = _events_ms(lambda: g.stz_step(dict(P, advect=1), dt, v, s, c), 3)
     sstar, _ = g.stz_step(P, dt, v, s, c)
     ph["rhs_ms"] = _events_ms(lambda: g.rhs(sstar, dt), 3)
     b = g.rhs(sstar, dt)
