@@ -140,6 +140,55 @@ def advection(sigma, v, h):
             + u[2] * eno_derivative(gz, u[2], h, -3))
 
 
+def node_laplacian(v, h):
+    """Eq. col_snd_deriv summed over x, y and z at the interior nodes (x, y
+    wrap; the z neighbours of the first and last interior planes are the
+    walls); zero on the wall planes."""
+    out = np.zeros_like(v)
+    c = v[:, 1:-1]
+    lx = np.roll(c, 1, axis=-1) + np.roll(c, -1, axis=-1) - 2.0 * c
+    ly = np.roll(c, 1, axis=-2) + np.roll(c, -1, axis=-2) - 2.0 * c
+    lz = v[:, 2:] + v[:, :-2] - 2.0 * c
+    out[:, 1:-1] = (lx + ly + lz) / (h * h)
+    return out
+
+
+def node_advection(v, h):
+    """(v . grad) v at the interior nodes, each component differentiated by
+    Eq. ENO along x, y and z with the node's own velocity; x and y wrap, and
+    the ghost node beyond a wall is the reflection 2 v_wall - v of the node
+    inside it (Sec. 3.5, Dirichlet walls).  Zero on the wall planes."""
+    out = np.zeros_like(v)
+    c = v[:, 1:-1]
+    gx = np.concatenate([c[..., -2:], c, c[..., :2]], axis=-1)
+    gy = np.concatenate([c[..., -2:, :], c, c[..., :2, :]], axis=-2)
+    gz = np.concatenate([2.0 * v[:, :1] - v[:, 1:2], v, 2.0 * v[:, -1:] - v[:, -2:-1]], axis=1)
+    for a in range(3):
+        out[a, 1:-1] = (c[0] * eno_derivative(gx[a], c[0], h, -1)
+                        + c[1] * eno_derivative(gy[a], c[1], h, -2)
+                        + c[2] * eno_derivative(gz[a], c[2], h, -3))
+    return out
+
+
+def explicit_step(v, sigma, chi, h, dt, lam, mu, p, U, rho, kappa):
+    """One forward-Euler step of the explicit method (Sec. 3.2), all terms
+    from the state of step n:
+      v'     = v + dt ((D_h sigma)/rho - (v . grad) v + kappa lap v)   (Eq. vel_evo_exp
+               per unit mass: the damping kappa = kappa' h is a kinematic
+               viscosity, which makes its units and the stability bound
+               dt <= h^2 / (6 kappa) consistent),
+      sigma' = sigma* + dt C : sym(G_h v), sigma* the STZ step with the
+               advection of Eq. stress_evo_exp (Truesdell term -tr(L) sigma
+               as everywhere else),
+      chi'   = the chi of the STZ step (Eq. chi_evo_exp);
+    walls of v' at (-U, 0, 0) and (+U, 0, 0) (Eq. u_bc)."""
+    acc = div_node(sigma, h) / rho - node_advection(v, h) + kappa * node_laplacian(v, h)
+    v_next = set_shear_walls(v + dt * acc, U)
+    sstar, chi_next = stz_step(v, sigma, chi, h, dt, lam, mu, dict(p, advect=1))
+    s_next = stress_update(sstar, v, h, dt, lam, mu)
+    return v_next, s_next, chi_next
+
+
 def chi_diffusion(sigma, chi, h, p):
     """div(D^pl grad chi) per cell for the state (sigma, chi) of step n."""
     sg, cg = z_ghosts(sigma), z_ghosts(chi)

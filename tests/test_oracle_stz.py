@@ -409,3 +409,51 @@ def test_advection_is_second_order_for_smooth_fields():
         adv = stz.advection(sigma, v, h)
         errs.append(np.abs(adv[:, 2:-2] - df[2:-2]).max())
     assert 3.3 < errs[0] / errs[1] < 4.7, errs
+
+
+def test_node_laplacian_and_advection_closed_forms():
+    """The explicit method's node operators: a Fourier mode in x is an
+    eigenfunction of the Laplacian with eigenvalue -(4/h^2) sin^2(pi m/nx);
+    a quadratic in z gives its second derivative exactly; a velocity linear
+    in z (v_x = a + b z, v_y = c + d z, v_z = w) has (v . grad) v = (w b, w d, 0)
+    exactly at every interior node, the ones next to the walls included (the
+    reflected ghost nodes continue a linear profile)."""
+    nx, ny, nz, h = 12, 6, 8, 0.125
+    i = np.arange(nx)[None, None, :]
+    k = np.arange(nz + 1)[:, None, None]
+    m = 3
+    f = np.cos(2 * np.pi * m * i / nx) * np.ones((nz + 1, ny, 1))
+    v = np.stack([f, 0 * f, 0 * f])
+    lap = stz.node_laplacian(v, h)
+    lam_ = -(4.0 / h**2) * np.sin(np.pi * m / nx) ** 2
+    assert np.allclose(lap[0, 1:-1], lam_ * f[1:-1], rtol=0, atol=1e-11)
+    assert not lap[:, 0].any() and not lap[:, -1].any()
+    q = (0.3 + 0.7 * (k * h) ** 2) * np.ones((1, ny, nx))
+    lap = stz.node_laplacian(np.stack([q, q, q]), h)
+    assert np.allclose(lap[:, 1:-1], 1.4, rtol=1e-12)
+    a, b, c, d, w = 0.2, -1.3, 0.5, 0.9, -0.4
+    z = k * h * np.ones((1, ny, nx))
+    v = np.stack([a + b * z, c + d * z, w + 0 * z])
+    adv = stz.node_advection(v, h)
+    assert np.allclose(adv[0, 1:-1], w * b, rtol=1e-12)
+    assert np.allclose(adv[1, 1:-1], w * d, rtol=1e-12)
+    assert np.abs(adv[2]).max() < 1e-15
+
+
+def test_explicit_step_simple_shear_from_rest():
+    """Sec. 3.2 on a linear shear profile between walls moving at -U and +U,
+    stress free and below yield: the velocity has no divergence of stress,
+    no curvature and no advection, so it stays; the stress takes
+    dt C : D with D_xz = U (the Truesdell terms vanish at sigma = 0), i.e.
+    sigma_xz = 2 mu U dt and nothing else; chi does not move."""
+    nx, ny, nz = 6, 4, 8
+    h, dt, U = 1.0 / nz, 0.01, 1e-3
+    v = shear_velocity(nx, ny, nz, U)
+    sigma = np.zeros((6, nz, ny, nx))
+    chi = np.full((nz, ny, nx), 0.03)
+    v1, s1, c1 = stz.explicit_step(v, sigma, chi, h, dt, LAM, MU, P, U, MU, 4.8 * h)
+    assert np.allclose(v1, v, rtol=0, atol=1e-18)
+    want = np.zeros_like(sigma)
+    want[4] = 2 * MU * U * dt
+    assert np.allclose(s1, want, rtol=1e-12, atol=1e-20)
+    assert np.array_equal(c1, chi)
