@@ -411,6 +411,65 @@ def weld_run(N: int = 256, steps: int = 12, both: bool = True) -> dict:
     return out
 
 
+def explicit_vs_qs(steps_e: int = 20000, steps_qs: int = 200, zeta: float = 1e4) -> dict:
+    """The explicit-versus-quasi-static comparison of Secs. 4.1-4.2 on its
+    64 x 64 x 32 grid (h = L/32): chi0 the cylindrical inclusion, tau0 scaled
+    to tau0/zeta and U_B = 1e-7 zeta L/t_s, ramped as U_B t/t_s over the first
+    t_s (Eq. u_bc), the sample at rest and free of stress at t = 0.
+    `steps_e` explicit steps (kappa = 4.8 h, dt = h^2/20, rho = mu/E) and
+    `steps_qs` quasi-static steps (dt = 200/zeta t_s, FP32-IR, rtol 1e-10)
+    are each timed between device synchronisations from t = 0, and scaled to
+    the paper's t_f = 2e6/zeta t_s."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import cylinder_chi, lame, shear_velocity, stz_constants
+    lam, mu = lame()
+    dev = torch.device("cuda:0")
+    nx, ny, nz = 64, 64, 32
+    h = 1.0 / nz
+    P = stz_constants()
+    P = dict(P, tau0=P["tau0"] / zeta)
+    UB, tf = 1e-7 * zeta, 2e6 / zeta
+    chi0 = torch.from_numpy(cylinder_chi(nx, ny, nz)).to(dev)
+    out = {"grid": [nx, ny, nz], "zeta": zeta, "t_f": tf}
+    for method in ("explicit", "quasi_static"):
+        g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=4, precision="fp32-ir", device=dev)
+        v = torch.from_numpy(shear_velocity(nx, ny, nz, 0.0)).to(dev)
+        s = torch.zeros((6, nz, ny, nx), dtype=torch.float64, device=dev)
+        c = chi0.clone()
+        if method == "explicit":
+            dt, n = h * h / 20.0, steps_e
+            kappa, rho = 4.8 * h, mu
+            g.explicit_step(P, dt, UB * min(dt, 1.0), rho, kappa, v, s, c)  # warm-up step
+            v.zero_(), s.zero_(), c.copy_(chi0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(n):
+                g.explicit_step(P, dt, UB * min((i + 1) * dt, 1.0), rho, kappa, v, s, c)
+            torch.cuda.synchronize()
+            cycles = None
+        else:
+            dt, n = 200.0 / zeta, steps_qs
+            g.projection_step(P, dt, UB * min(dt, 1.0), v, s, c, rtol=1e-10)  # warm-up step
+            v.zero_(), s.zero_(), c.copy_(chi0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cycles = [g.projection_step(P, dt, UB * min((i + 1) * dt, 1.0), v, s, c,
+                                        rtol=1e-10).cycles for i in range(n)]
+            torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[method] = {"dt": dt, "steps": n, "t_end": n * dt, "ms_per_step": sec * 1e3 / n,
+                       "steps_to_t_f": tf / dt, "projected_s_to_t_f": sec / n * tf / dt,
+                       "sigma_xz_mean_at_end": s[4].mean().item()}
+        if cycles is not None:
+            out[method]["vcycles_per_step"] = sum(cycles) / n
+        g.close()
+        del v, s, c
+    torch.cuda.empty_cache()
+    return out
+
+
 TABLE3_S_PER_VCYCLE = {128: 0.22, 256: 0.76, 384: 2.08, 512: 3.87, 768: 13.88}
 
 
@@ -529,6 +588,8 @@ def main():
                     help="only run the single-defect and welding blocks and print them")
     ap.add_argument("--no-table3", action="store_true",
                     help="skip the V-cycle timing on the paper's N x N x N/2 grids (N = 128..768)")
+    ap.add_argument("--explicit-only", action="store_true",
+                    help="only run the explicit-versus-quasi-static block (64 x 64 x 32)")
     ap.add_argument("--table3-only", action="store_true",
                     help="only time V-cycles on the paper's N x N x N/2 grids and print them")
     ap.add_argument("--profile-solve", action="store_true",
@@ -553,12 +614,16 @@ def main():
     if args.profile_solve:
         profile_solve(args.n)
         return
+    if args.explicit_only:
+        print(json.dumps({"explicit_vs_qs_64x64x32": explicit_vs_qs()}))
+        return
     if args.table3_only:
         print(json.dumps({"table3_shapes": table3_shapes()}))
         return
     if args.defect_only:
         print(json.dumps({"defect_256x256x128": defect_run(steps=args.defect_steps),
-                          "weld_256x256x64": weld_run()}))
+                          "weld_256x256x64": weld_run(),
+                          "explicit_vs_qs_64x64x32": explicit_vs_qs()}))
         return
     n = args.n
     h = 1.0 / n
@@ -653,6 +718,7 @@ def main():
         out["defect_256x256x128"] = defect_run(steps=args.defect_steps)
     if not args.no_defect and n == 256:
         out["weld_256x256x64"] = weld_run()
+        out["explicit_vs_qs_64x64x32"] = explicit_vs_qs()
     if not args.no_table3 and n == 256:
         out["table3_shapes"] = table3_shapes()
     if not args.no_cpu_baseline:

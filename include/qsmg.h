@@ -215,6 +215,25 @@ qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp,
                                    double* sigma, double* chi, void* scratch, double rtol,
                                    int max_cycles, qs_solve_info* info);
 
+/* One forward-Euler step of the explicit method (Sec. 3.2), in place, every
+ * term from the state of step n:
+ *   v'     = v + dt ((D_h sigma)/rho - (v . grad) v + kappa lap v)
+ *            at interior nodes (Eq. vel_evo_exp per unit mass: kappa is a
+ *            kinematic viscosity, kappa = kappa' h in the paper's runs, with
+ *            the bound dt <= h^2/(6 kappa)); the Laplacian by Eq. col_snd_deriv,
+ *            the advection by Eq. ENO with the node's own velocity and a
+ *            ghost node 2 v_wall - v past each wall (Sec. 3.5);
+ *            walls (-U,0,0) at k = 0 and (+U,0,0) at k = nz (Eq. u_bc);
+ *   sigma' = sigma* + dt C : sym(G_h v) with sigma* from qs_stz_step with
+ *            advect = 1 (Eq. stress_evo_exp; Truesdell term -tr(L) sigma);
+ *   chi'   = chi' of that STZ step (Eq. chi_evo_exp).
+ * sp->advect is ignored (always on); n_sub and l_diff act as in
+ * qs_stz_step.  rho > 0 is the density in units of E t_s^2 / L^2 (mu/E when
+ * t_s = L / c_s).  `scratch`: qs_step_scratch_bytes() bytes, 256-aligned.
+ * No solve and no host synchronisation; nz >= 2. */
+qs_status qs_explicit_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double rho,
+                           double kappa, double* v, double* sigma, double* chi, void* scratch);
+
 /* Adjoint building blocks (reverse mode of one step; plain Euclidean inner
  * products on the stored arrays, so Voigt off-diagonals are single entries).
  *  qs_stz_step_vjp:      given g_sstar (6 cells) and g_chi1 (cells), return

@@ -69,6 +69,7 @@ SIGNATURES = {
                            C.POINTER(QSSolveInfo)],
     "qs_projection_step_walls": [_P, C.POINTER(QSStzParams), _P, _P, _P, _P, _P, _P, _D, _I,
                                  C.POINTER(QSSolveInfo)],
+    "qs_explicit_step": [_P, C.POINTER(QSStzParams), _D, _D, _D, _P, _P, _P, _P],
     "qs_stz_step_vjp": [_P, C.POINTER(QSStzParams), _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "qs_rhs_vjp": [_P, _P, _D, _P],
     "qs_stress_update_vjp": [_P, _P, _D, _P],

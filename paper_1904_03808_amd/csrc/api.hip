@@ -806,6 +806,29 @@ qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp, const
                               max_cycles, info);
 }
 
+qs_status qs_explicit_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double rho,
+                           double kappa, double* v, double* sigma, double* chi, void* scratch) {
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || !(rho > 0.0) ||
+      !std::isfinite(rho) || !(kappa >= 0.0) || !std::isfinite(kappa) || !std::isfinite(U_wall))
+    return QS_ERR_ARG;
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
+  const Dims d = hd->L[0].d;
+  if (d.nz < 2) return QS_ERR_SHAPE;
+  Carver cv{static_cast<char*>(scratch)};
+  double* sstar = cv.take<double>(6 * cells(d));
+  double* chi1 = cv.take<double>(cells(d));
+  double* vnew = cv.take<double>(d.elems());
+  StzArgs a = stz_args(hd, sp);
+  a.advect = 1;  // the stress equation of the explicit method carries the advection
+  launch_stz_step(v, sigma, chi, sstar, chi1, d, a, hd->stream);
+  launch_explicit_velocity(v, sigma, vnew, d, hd->p.h, sp->dt, rho, kappa, hd->stream);
+  launch_set_walls(vnew, d, U_wall, hd->stream);
+  launch_stress_update(sstar, v, sigma, d, hd->p.h, sp->dt, hd->p.lambda, hd->p.mu, hd->stream);
+  QS_HIP(hipMemcpyAsync(v, vnew, d.elems() * sizeof(double), hipMemcpyDeviceToDevice, hd->stream));
+  QS_HIP(hipMemcpyAsync(chi, chi1, cells(d) * sizeof(double), hipMemcpyDeviceToDevice, hd->stream));
+  return launch_check();
+}
+
 qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* v,
                           const double* sigma, const double* chi, const double* g_sstar,
                           const double* g_chi1, double* g_sigma, double* g_chi, double* g_v,

@@ -151,6 +151,8 @@ void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hip
 void launch_stress_update(const double* sstar, const double* v, double* out, Dims d, double h,
                           double dt, double lam, double mu, hipStream_t s);
 void launch_set_walls(double* v, Dims d, double U, hipStream_t s);
+void launch_explicit_velocity(const double* v, const double* sigma, double* vout, Dims d, double h,
+                              double dt, double rho, double kappa, hipStream_t s);
 void launch_copy_walls(double* v, const double* lo, const double* hi, Dims d, hipStream_t s);
 void launch_stz_step_vjp(const double* v, const double* sigma, const double* chi,
                          const double* g_sstar, const double* g_chi1, double* g_sigma,

@@ -392,6 +392,67 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ sstar, d
   for (int a = 0; a < 3; ++a) b[a * C + o] = acc[a] * scale;
 }
 
+// Explicit method (Sec. 3.2): the new velocity at an interior node,
+//   v' = v + dt ((D_h sigma)/rho - (v . grad) v + kappa lap v),
+// all from step n: D_h sigma as in k_rhs, the Laplacian by Eq. col_snd_deriv,
+// the advection by Eq. ENO with the node's own velocity (ghost node past a
+// wall: 2 v_wall - v of the node inside it).  Writes interior nodes of vout.
+__global__ __launch_bounds__(256) void k_explicit_velocity(const double* __restrict__ v,
+                                                           const double* __restrict__ sigma,
+                                                           double* __restrict__ vout, int nx, int ny,
+                                                           int nz, double h, double dt, double rho,
+                                                           double kappa) {
+  int i, j, k;
+  NodeCells nc;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!node_of(t, nx, ny, nz, &i, &j, &k, &nc)) return;
+  const int N = nx * ny * nz, P = nx * ny, C = (nz + 1) * P;
+  double div[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    double g[2][2][2];
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) g[ez][ey][ex] = sigma[n * N + nc.cell[ez][ey][ex]];
+    const int p = VA[n], q = VB[n];
+    div[p] += node_diff(g, q);
+    if (p != q) div[q] += node_diff(g, p);
+  }
+  const int o = k * P + j * nx + i;
+  const int row = o - i;
+  const double u[3] = {v[o], v[C + o], v[2 * C + o]};
+  const double h2 = 2.0 * h;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double* f = v + a * C;
+    double g[5];
+#pragma unroll
+    for (int s = -2; s <= 2; ++s) g[s + 2] = f[row + (i + s + 2 * nx) % nx];
+    const double dx = eno_2h(g[0], g[1], g[2], g[3], g[4], u[0]);
+    const double lx = g[1] + g[3] - 2.0 * g[2];
+#pragma unroll
+    for (int s = -2; s <= 2; ++s) g[s + 2] = f[k * P + ((j + s + 2 * ny) % ny) * nx + i];
+    const double dy = eno_2h(g[0], g[1], g[2], g[3], g[4], u[1]);
+    const double ly = g[1] + g[3] - 2.0 * g[2];
+    const int col = j * nx + i;
+#pragma unroll
+    for (int s = -2; s <= 2; ++s) {
+      const int e = k + s;
+      g[s + 2] = e < 0 ? 2.0 * f[col] - f[P + col]
+                       : (e > nz ? 2.0 * f[nz * P + col] - f[(nz - 1) * P + col] : f[e * P + col]);
+    }
+    const double dz = eno_2h(g[0], g[1], g[2], g[3], g[4], u[2]);
+    const double lz = g[3] + g[1] - 2.0 * g[2];
+    const double adv = u[0] * (dx / h2) + u[1] * (dy / h2) + u[2] * (dz / h2);
+    const double lap = (lx + ly + lz) / (h * h);
+    const double acc = (div[a] * (0.25 / h)) / rho - adv + kappa * lap;
+    vout[a * C + o] = g[2] + dt * acc;
+  }
+}
+
 __global__ void k_zero_walls(double* __restrict__ b, int nx, int ny, int nz) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int P = nx * ny;
@@ -695,6 +756,13 @@ void launch_stress_update(const double* sstar, const double* v, double* out, Dim
   const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
   hipLaunchKernelGGL(k_stress_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, sstar, v, out,
                      d.nx, d.ny, d.nz, h, dt, lam, mu);
+}
+
+void launch_explicit_velocity(const double* v, const double* sigma, double* vout, Dims d, double h,
+                              double dt, double rho, double kappa, hipStream_t s) {
+  const long long n = static_cast<long long>(d.nx) * d.ny * (d.nz - 1);
+  hipLaunchKernelGGL(k_explicit_velocity, dim3(blocks_for(n, 256)), dim3(256), 0, s, v, sigma, vout,
+                     d.nx, d.ny, d.nz, h, dt, rho, kappa);
 }
 
 void launch_set_walls(double* v, Dims d, double U, hipStream_t s) {

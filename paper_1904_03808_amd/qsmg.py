@@ -198,6 +198,17 @@ class MGSolver:
         n = min(info.cycles + 1, _capi.QS_HIST)
         return SolveInfo(st, info.cycles, info.levels, info.rel_res, list(info.rel_res_hist[:n]))
 
+    def explicit_step(self, params: dict, dt: float, U: float, rho: float, kappa: float, v, sigma,
+                      chi) -> None:
+        """In-place step n -> n+1 of the explicit method (no solve)."""
+        cs = self.cell_shape
+        sp = _stz(params, dt)
+        check(self._lib.qs_explicit_step(self._h, C.byref(sp), float(U), float(rho), float(kappa),
+                                         self._chk(v, self.node_shape(), "v"),
+                                         self._chk(sigma, (6,) + cs, "sigma"),
+                                         self._chk(chi, cs, "chi"),
+                                         C.c_void_p(self._scratch_buf())), "qs_explicit_step")
+
     # -- reverse mode -------------------------------------------------------------
     def stz_step_vjp(self, params: dict, dt: float, v, sigma, chi, g_sstar, g_chi1, g_v):
         """Returns (g_sigma, g_chi) and adds the velocity cotangent into g_v."""

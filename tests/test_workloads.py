@@ -80,3 +80,20 @@ def test_weld_walls_follow_the_spinning_disc():
     assert np.all(f[~inside] < 1.0) and np.all(f[~inside] > 0.0)
     lo2, hi2 = W.weld_walls(nx, ny, nz, omega, h, top=True, bottom=True)
     assert np.array_equal(lo2, hi2) and np.array_equal(hi2, hi)
+
+
+def test_cylinder_chi_follows_the_inclusion():
+    """Sec. 4.1: 800 K on the cylinder's axis (limit at the centre cells),
+    600 K outside |x| < L/2 and far from the axis; constant along x inside;
+    mirror-symmetric in y and z."""
+    nx, ny, nz = 64, 64, 32
+    chi = W.cylinder_chi(nx, ny, nz) * 21000.0
+    h = 1.0 / nz
+    xc = (np.arange(nx) + 0.5 - nx / 2) * h
+    inside = np.abs(xc) < 0.5
+    assert np.all(chi[:, :, ~inside] == 600.0)
+    assert np.all(chi[:, :, inside] == chi[:, :, inside][:, :, :1])
+    top = 600.0 + 200.0 * np.exp(-500.0 * 2 * (h / 2) ** 2)
+    assert np.isclose(chi.max(), top, rtol=1e-14)
+    assert np.array_equal(chi, chi[::-1]) and np.array_equal(chi, chi[:, ::-1])
+    assert chi[0, 0, nx // 2] - 600.0 < 1e-9

@@ -221,6 +221,20 @@ def shear_velocity(nx: int, ny: int, nz: int, U: float) -> np.ndarray:
     return v
 
 
+def cylinder_chi(nx: int, ny: int, nz: int, ez_K: float = 21000.0) -> np.ndarray:
+    """The finite cylindrical inclusion of the explicit-versus-quasi-static
+    comparison (paper Sec. 4.1): 600 K + 200 K exp(-500 (y^2 + z^2)/L^2) where
+    |x| < L/2, 600 K elsewhere, in units of e_z/k_B; coordinates of the cell
+    centres from the sample's centre, h = 1/nz, L = nz h."""
+    h = 1.0 / nz
+    zc = (np.arange(nz) + 0.5 - 0.5 * nz) * h
+    yc = (np.arange(ny) + 0.5 - 0.5 * ny) * h
+    xc = (np.arange(nx) + 0.5 - 0.5 * nx) * h
+    r2 = zc[:, None, None] ** 2 + yc[None, :, None] ** 2 + 0.0 * xc[None, None, :]
+    inside = np.abs(xc)[None, None, :] < 0.5
+    return (600.0 + np.where(inside, 200.0 * np.exp(-500.0 * r2), 0.0)) / ez_K
+
+
 def defect_state(nx: int, ny: int, nz: int, U: float = 1e-7) -> dict:
     """Initial (v, sigma, chi) of the single-defect run (paper Sec. 4.4): the
     sample at rest and free of stress, chi from Eq. case0_chi.  The wall speed
