@@ -47,7 +47,8 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for required in ("qs_setup", "qs_destroy", "qs_apply", "qs_mg_solve", "qs_stz_step", "qs_rhs",
                      "qs_stress_update", "qs_projection_step", "qs_stz_step_vjp", "qs_rhs_vjp",
-                     "qs_stress_update_vjp", "qs_workspace_bytes", "qs_status_string"):
+                     "qs_stress_update_vjp", "qs_workspace_bytes", "qs_status_string",
+                     "qs_projection_step_walls", "qs_explicit_step"):
         assert required in names
 
 
@@ -122,3 +123,12 @@ def test_workspace_sizing_and_argument_errors(lib):
     # null handles are refused before anything touches a device
     assert lib.qs_destroy(None) == _capi.QS_ERR_ARG
     assert lib.qs_mg_solve(None, None, None, C.c_double(1e-10), 10, None) == _capi.QS_ERR_ARG
+    from workloads import stz_constants
+    P = stz_constants()
+    sp = _capi.QSStzParams(P["s_y"], P["tau0"], P["beta"], P["delta_over_T"], P["c0"],
+                           P["chi_inf"], 1.0, 0.0, 1, 0)
+    assert lib.qs_explicit_step(None, C.byref(sp), 0.0, 0.37, 0.1, None, None, None,
+                                None) == _capi.QS_ERR_ARG
+    assert lib.qs_projection_step_walls(None, C.byref(sp), None, None, None, None, None, None,
+                                        C.c_double(1e-10), 10, None) == _capi.QS_ERR_ARG
+    assert lib.qs_stz_step(None, C.byref(sp), None, None, None, None, None) == _capi.QS_ERR_ARG
