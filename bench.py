@@ -253,8 +253,34 @@ def config4_adjoint(n: int = 96, steps: int = 10) -> dict:
             "loss": loss.item(), "solver": "fp64, rtol 1e-10 forward and transposed"}
 
 
+# The paper's simple-shear runs on N x N x N/2 grids (dt = 200 t_s, U = 1e-7
+# L/t_s, 5000 steps to 1e6 t_s, 32 CPU processes): chi0, diffusion length in
+# cells, and the reported (total hours, V-cycle hours, V-cycles) per N.
+PAPER_RUNS = {
+    "defect": {"chi": "Eq. case0_chi (550 K + 170 K Gaussian)", "l_cells": 1.0,
+               "paper": {256: (7.52, 5.852, 17586)}},
+    "random": {"chi": "Eq. convolve, 550 K mean, 15 K std, l_c = 10 h, cutoff 5 (seed 7)",
+               "l_cells": 1.5,
+               "paper": {128: (1.61, 1.27, 20480), 256: (6.12, 3.89, 18367),
+                         384: (22.44, 14.28, 24675), 512: (42.86, 30.23, 28175),
+                         768: (105.97, 75.90, 19689)}},
+    "helix": {"chi": "Eq. case12_chi (550 K + 200 K along the helix)", "l_cells": 1.5,
+              "paper": {80: (1.52, 1.00, 15073), 128: (1.94, 1.37, 16511),
+                        256: (3.69, 2.75, 17939)}},
+}
+
+
+def paper_chi(kind: str, nx: int, ny: int, nz: int):
+    from workloads import chi_field, defect_chi, helix_chi
+    if kind == "defect":
+        return defect_chi(nx, ny, nz)
+    if kind == "helix":
+        return helix_chi(nx, ny, nz)
+    return chi_field(nx, ny, nz, 7, 550.0 / 21000, 15.0 / 21000, 10.0)
+
+
 def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: int = -1,
-               per_vcycle: bool = True) -> dict:
+               per_vcycle: bool = True, kind: str = "defect", chi_wall: int = 0) -> dict:
     """The single-defect run of Sec. 4.4 on its N x N x N/2 grid (h = L/(N/2)):
     chi from Eq. case0_chi, l = h, dt = 200 t_s, U = 1e-7 L/t_s, the sample at
     rest and free of stress at t = 0.  `steps` FP32-IR projection steps
@@ -267,7 +293,8 @@ def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: i
     so at most about 1850 steps can be run that way.  Then the time per V-cycle at this
     shape, FP32-IR and FP64, from solves from zero of a D_h sigma right-hand
     side (seed 2): the figure the paper tabulates (Tables 2 and 3, and the
-    single-defect run's V-cycle total)."""
+    single-defect run's V-cycle total).  `kind` = "random" or "helix" runs the
+    Table 3 or Table 2 workload instead (l = 1.5 h)."""
     import torch
 
     from paper_1904_03808_amd.qsmg import MGSolver
@@ -276,8 +303,11 @@ def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: i
     dev = torch.device("cuda:0")
     nx, ny, nz = N, N, N // 2
     h = 1.0 / nz
-    P, dt, U = dict(stz_constants(), l_diff=h, n_sub=n_sub), 200.0, 1e-7
+    run = PAPER_RUNS[kind]
+    P, dt, U = (dict(stz_constants(), l_diff=run["l_cells"] * h, n_sub=n_sub, chi_wall=chi_wall),
+                200.0, 1e-7)
     st = defect_state(nx, ny, nz, U)
+    st["chi"] = paper_chi(kind, nx, ny, nz)
     g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=min_coarse_nz, precision="fp32-ir",
                  device=dev)
     v0, s0, c0 = (torch.from_numpy(st[k]).to(dev) for k in ("v", "sigma", "chi"))
@@ -287,20 +317,30 @@ def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: i
     v.copy_(v0), s.copy_(s0), c.copy_(c0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    marks, cycles = [t0], []
+    marks, cycles, failed = [t0], [], None
     # U(t) ramps to U_B over the first t_s < dt, so every step sees U_B
+    from paper_1904_03808_amd._capi import QSError
     for i in range(steps):
-        cycles.append(g.projection_step(P, dt, U, v, s, c, rtol=1e-10).cycles)
+        try:
+            cycles.append(g.projection_step(P, dt, U, v, s, c, rtol=1e-10).cycles)
+        except QSError as e:  # a non-finite state: report the steps that ran
+            failed = {"step": i, "status": str(e)}
+            torch.cuda.synchronize()
+            marks.append(time.perf_counter())
+            break
         if (i + 1) % 500 == 0 or i + 1 == steps:
             torch.cuda.synchronize()
             marks.append(time.perf_counter())
             if steps > 1500:
-                print("defect run: %d steps, %.1f s" % (i + 1, marks[-1] - t0), file=sys.stderr,
+                print("%s run: %d steps, %.1f s" % (kind, i + 1, marks[-1] - t0), file=sys.stderr,
                       flush=True)
+    steps = max(len(cycles), 1)
     ms = (marks[-1] - t0) * 1e3 / steps
     phases = []
     for m in range(len(marks) - 1):
         a, b = 500 * m, min(500 * (m + 1), steps)
+        if b <= a:
+            continue
         phases.append({"steps": [a, b], "ms_per_step": (marks[m + 1] - marks[m]) * 1e3 / (b - a),
                        "vcycles_per_step": sum(cycles[a:b]) / (b - a)})
     p_ = (s[0] + s[1] + s[2]) / 3
@@ -319,12 +359,17 @@ def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: i
            "plastic_substeps": ("single step (Eq. sig_star_qs)" if n_sub == 1 else
                                 "per cell from the stability bound" if n_sub == -1 else n_sub),
            "solver": "fp32-ir, rtol 1e-10",
-           "inputs": "chi Eq. case0_chi (550 K + 170 K Gaussian), sigma = 0, v = 0 at t = 0; "
-                     "l = h, dt = 200 t_s, U = 1e-7 L/t_s",
-           "paper_context_32_cpu_processes": {
-               "s_per_vcycle_table3": 0.76, "s_per_vcycle_table2": 0.55,
-               "single_defect_run": {"steps": 5000, "hours": 7.52, "vcycle_hours": 5.852,
-                                     "vcycles": 17586}}}
+           "workload": kind, "failed": failed, "chi_wall": chi_wall,
+           "inputs": "chi %s, sigma = 0, v = 0 at t = 0; l = %g h, dt = 200 t_s, U = 1e-7 L/t_s"
+                     % (run["chi"], run["l_cells"]),
+           "seconds": ms * steps / 1e3}
+    if N in run["paper"]:
+        hours, vc_hours, vcycles = run["paper"][N]
+        res["paper_context_32_cpu_processes"] = {
+            "steps": 5000, "hours": hours, "vcycle_hours": vc_hours, "vcycles": vcycles,
+            "s_per_vcycle": vc_hours * 3600 / vcycles}
+        if steps == 5000:
+            res["paper_hours_over_ours"] = hours * 3600 / res["seconds"]
     if not per_vcycle:
         torch.cuda.empty_cache()
         return res
@@ -588,6 +633,12 @@ def main():
                     help="only run the single-defect and welding blocks and print them")
     ap.add_argument("--no-table3", action="store_true",
                     help="skip the V-cycle timing on the paper's N x N x N/2 grids (N = 128..768)")
+    ap.add_argument("--paper-run", choices=sorted(PAPER_RUNS),
+                    help="only run one of the paper's simple-shear runs (see --paper-n, "
+                         "--defect-steps) and print it")
+    ap.add_argument("--paper-n", type=int, default=256, help="N of the N x N x N/2 grid")
+    ap.add_argument("--chi-wall", type=int, default=0, choices=(0, 1),
+                    help="chi diffusion at the walls: 0 ghost-state D^pl, 1 the wall cell's own")
     ap.add_argument("--explicit-only", action="store_true",
                     help="only run the explicit-versus-quasi-static block (64 x 64 x 32)")
     ap.add_argument("--table3-only", action="store_true",
@@ -613,6 +664,11 @@ def main():
         return
     if args.profile_solve:
         profile_solve(args.n)
+        return
+    if args.paper_run:
+        print(json.dumps({"paper_run": defect_run(N=args.paper_n, steps=args.defect_steps,
+                                                  kind=args.paper_run, per_vcycle=False,
+                                                  chi_wall=args.chi_wall)}))
         return
     if args.explicit_only:
         print(json.dumps({"explicit_vs_qs_64x64x32": explicit_vs_qs()}))

@@ -111,6 +111,10 @@ typedef struct {
   int advect;              /* 0 (Eq. sig_star_qs) or 1: sigma* also carries
                               -dt (v . grad) sigma (qs_stz_step); the reverse-
                               mode entry points require 0                     */
+  int chi_wall;            /* chi diffusion at the walls (qs_stz_step): 0, the
+                              face to the ghost cell carries the mean of the
+                              cell's D^pl and D^pl of the extrapolated ghost
+                              state; 1, the wall faces carry no flux          */
 } qs_stz_params;
 
 typedef struct qs_handle qs_handle;
@@ -162,7 +166,8 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol,
  * h^2; x and y wrap; below the first and above the last cell layer a ghost
  * layer holds the linear extrapolation of sigma and chi from the two nearest
  * layers (Sec. 3.5), with D^pl evaluated on it (0 where the extrapolated chi
- * is not positive).  D^pl, sbar and chi are those of step n.
+ * is not positive; with chi_wall = 1 the wall faces carry no flux instead).
+ * D^pl, sbar and chi are those of step n.
  * Sub-steps (an extension; the paper takes the single step above): with
  * n_sub = M > 1, or n_sub = -1 and M = ceil(4 mu dt dD^pl/dsbar) at the state
  * of step n clamped to [1, 65536] per cell, the plastic terms take M forward-

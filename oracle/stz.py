@@ -16,7 +16,8 @@ Readings where the paper is silent or inconsistent (also in the design notes):
     ghost layer of sigma and chi is the linear extrapolation of the two
     nearest layers (Sec. 3.5), and D^pl there is evaluated on the ghost
     values (D^pl = 0 where the extrapolated chi is not positive); x and y
-    wrap; l = 0 leaves the term out;
+    wrap; l = 0 leaves the term out; p["chi_wall"] = 1 (not the paper's)
+    closes the wall faces to the flux instead;
   * Eq. sig_star_qs has no advection term, so none is applied.
 """
 from __future__ import annotations
@@ -190,11 +191,17 @@ def explicit_step(v, sigma, chi, h, dt, lam, mu, p, U, rho, kappa):
 
 
 def chi_diffusion(sigma, chi, h, p):
-    """div(D^pl grad chi) per cell for the state (sigma, chi) of step n."""
+    """div(D^pl grad chi) per cell for the state (sigma, chi) of step n.
+    With p["chi_wall"] = 1 the wall faces carry no flux: the ghost layers
+    take the chi of the cell next to them, so the difference across a wall
+    face is zero (an extension; see the module's readings)."""
     sg, cg = z_ghosts(sigma), z_ghosts(chi)
     _, sbar = deviator(voigt_to_full(sg))
     pos = np.real(cg) > 0.0
     D = np.where(pos, plastic_rate(sbar, np.where(pos, cg, 1.0), p), 0.0)
+    if p.get("chi_wall", 0):
+        cg = cg.copy()
+        cg[0], cg[-1] = cg[1], cg[-2]
     return flux_divergence(D, cg, h)
 
 

@@ -39,7 +39,7 @@ class QSStzParams(C.Structure):
     _fields_ = [("s_y", C.c_double), ("tau0", C.c_double), ("beta", C.c_double),
                 ("delta_over_T", C.c_double), ("c0", C.c_double), ("chi_inf", C.c_double),
                 ("dt", C.c_double), ("l_diff", C.c_double), ("n_sub", C.c_int),
-                ("advect", C.c_int)]
+                ("advect", C.c_int), ("chi_wall", C.c_int)]
 
 
 class QSError(RuntimeError):

@@ -679,7 +679,7 @@ namespace {
 bool valid_stz(const qs_stz_params* sp) {
   return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt) &&
          sp->l_diff >= 0.0 && std::isfinite(sp->l_diff) && sp->n_sub >= -1 &&
-         (sp->advect == 0 || sp->advect == 1);
+         (sp->advect == 0 || sp->advect == 1) && (sp->chi_wall == 0 || sp->chi_wall == 1);
 }
 
 StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
@@ -697,6 +697,7 @@ StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
   a.l2 = sp->l_diff * sp->l_diff;
   a.n_sub = sp->n_sub <= 1 && sp->n_sub >= 0 ? 1 : sp->n_sub;
   a.advect = sp->advect;
+  a.chi_wall = sp->chi_wall;
   return a;
 }
 

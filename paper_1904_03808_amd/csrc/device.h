@@ -144,6 +144,7 @@ struct StzArgs {
   double l2;  // squared diffusion length of Eq. chi_evo (0: no diffusion term)
   int n_sub;  // plastic sub-steps: 1 single step, > 1 fixed count, -1 per cell
   int advect; // 1: sigma* carries the advection -(v . grad) sigma (Eq. ENO)
+  int chi_wall;  // 1: no chi diffusion flux through the wall faces
 };
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
                      double* chi1, Dims d, const StzArgs& a, hipStream_t s);

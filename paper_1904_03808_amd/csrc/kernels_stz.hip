@@ -226,6 +226,9 @@ __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__
   if (c.k > 0) {
     Dn = dpl_cell(sigma, chi, N, o - P, a);
     xn = chi[o - P];
+  } else if (a.chi_wall) {  // no flux through the wall face
+    Dn = Dc;
+    xn = xc;
   } else {
     Dn = dpl_ghost(sigma, chi, N, o, o + P, a, &xn);
   }
@@ -233,6 +236,9 @@ __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__
   if (c.k < nz - 1) {
     Dn = dpl_cell(sigma, chi, N, o + P, a);
     xn = chi[o + P];
+  } else if (a.chi_wall) {
+    Dn = Dc;
+    xn = xc;
   } else {
     Dn = dpl_ghost(sigma, chi, N, o, o - P, a, &xn);
   }

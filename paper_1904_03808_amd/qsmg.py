@@ -47,7 +47,8 @@ def _ptr(t: torch.Tensor) -> int:
 def _stz(params: dict, dt: float) -> QSStzParams:
     return QSStzParams(params["s_y"], params["tau0"], params["beta"], params["delta_over_T"],
                        params["c0"], params["chi_inf"], dt, params.get("l_diff", 0.0),
-                       int(params.get("n_sub", 1)), int(bool(params.get("advect", 0))))
+                       int(params.get("n_sub", 1)), int(bool(params.get("advect", 0))),
+                       int(params.get("chi_wall", 0)))
 
 
 class MGSolver:

@@ -126,7 +126,7 @@ def test_workspace_sizing_and_argument_errors(lib):
     from workloads import stz_constants
     P = stz_constants()
     sp = _capi.QSStzParams(P["s_y"], P["tau0"], P["beta"], P["delta_over_T"], P["c0"],
-                           P["chi_inf"], 1.0, 0.0, 1, 0)
+                           P["chi_inf"], 1.0, 0.0, 1, 0, 0)
     assert lib.qs_explicit_step(None, C.byref(sp), 0.0, 0.37, 0.1, None, None, None,
                                 None) == _capi.QS_ERR_ARG
     assert lib.qs_projection_step_walls(None, C.byref(sp), None, None, None, None, None, None,

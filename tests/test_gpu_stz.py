@@ -87,8 +87,8 @@ def test_stz_step_with_chi_diffusion(n):
     sig[4] = P["s_y"] * (1.03 + 0.01 * np.sin(2 * np.pi * x * nz / nx) * np.cos(np.pi * z))
     sig[0] = 1e-3 * np.cos(2 * np.pi * y * nz / ny)
     chi = 0.05 + 0.008 * np.exp(-200.0 * (x * x + y * y + z * z))
-    for l in (h, 1.5 * h):
-        p = dict(P, l_diff=l)
+    for l, cw in ((h, 0), (1.5 * h, 0), (h, 1)):
+        p = dict(P, l_diff=l, chi_wall=cw)
         dt = 10.0
         ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
         rs, rc = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, p)

@@ -457,3 +457,28 @@ def test_explicit_step_simple_shear_from_rest():
     want[4] = 2 * MU * U * dt
     assert np.allclose(s1, want, rtol=1e-12, atol=1e-20)
     assert np.array_equal(c1, chi)
+
+
+def test_chi_diffusion_closed_walls_conserve_chi():
+    """chi_wall = 1: with sigma and chi constant in x and y the x, y faces
+    carry no flux and the interior z faces cancel in the column sum, so with
+    closed wall faces the column sum vanishes; with chi_wall = 0 the two
+    wall faces remain, each carrying the mean of its cell's D^pl and the
+    ghost state's times the extrapolated difference."""
+    nx, ny, nz, h = 3, 2, 6, 0.2
+    z = np.arange(nz)
+    sigma = np.zeros((6, nz, ny, nx))
+    sigma[4] = (P["s_y"] * (1.05 + 0.04 * z + 0.01 * z * z))[:, None, None]
+    chi = np.broadcast_to((0.03 + 0.002 * z + 0.0005 * z * z)[:, None, None], (nz, ny, nx)).copy()
+    p1 = dict(P, chi_wall=1)
+    t1 = stz.chi_diffusion(sigma, chi, h, p1)
+    assert abs(t1[:, 0, 0].sum()) <= 1e-12 * np.abs(t1).max()
+    assert np.allclose(t1, t1[:, :1, :1], rtol=1e-14)
+    t0 = stz.chi_diffusion(sigma, chi, h, P)
+    assert np.array_equal(t0[1:-1], t1[1:-1])
+    sg = stz.z_ghosts(sigma)
+    _, sb = stz.deviator(voigt_to_full(sg))
+    D = stz.plastic_rate(sb, stz.z_ghosts(chi), P)[:, 0, 0]
+    c = chi[:, 0, 0]
+    want = (0.5 * (D[1] + D[0]) * (c[0] - c[1]) + 0.5 * (D[-2] + D[-1]) * (c[-1] - c[-2])) / h**2
+    assert np.isclose(t0[:, 0, 0].sum(), want, rtol=1e-10)

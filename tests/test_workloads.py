@@ -97,3 +97,23 @@ def test_cylinder_chi_follows_the_inclusion():
     assert np.isclose(chi.max(), top, rtol=1e-14)
     assert np.array_equal(chi, chi[::-1]) and np.array_equal(chi, chi[:, ::-1])
     assert chi[0, 0, nx // 2] - 600.0 < 1e-9
+
+
+def test_helix_chi_follows_eq_case12_chi():
+    """Eq. case12_chi: in every y-row of cells the field peaks where x and z
+    are nearest the helix centre line (cos(6 pi (y+1))/8 - 1/16,
+    sin(4 pi (y+1))/8 - 1/16), falls to 550 K far from it, and repeats in y
+    with the periods 1/3 (x offset) and 1/2 (z offset), so with period 1 on
+    the sample's y range [-1, 1)."""
+    nx, ny, nz = 64, 64, 32
+    chi = W.helix_chi(nx, ny, nz) * 21000.0
+    h = 1.0 / nz
+    c = lambda n: (np.arange(n) + 0.5 - n / 2) * h
+    xc, yc, zc = c(nx), c(ny), c(nz)
+    for jj in (0, 17, 40):
+        k, i = np.unravel_index(np.argmax(chi[:, jj, :]), (nz, nx))
+        x0 = np.cos(6 * np.pi * (yc[jj] + 1)) / 8 - 1 / 16
+        z0 = np.sin(4 * np.pi * (yc[jj] + 1)) / 8 - 1 / 16
+        assert abs(xc[i] - x0) <= h / 2 + 1e-12 and abs(zc[k] - z0) <= h / 2 + 1e-12
+    assert np.allclose(chi[:, :ny // 2], chi[:, ny // 2:], rtol=1e-13)
+    assert chi.min() >= 550.0 and chi.min() - 550.0 < 1e-6 and chi.max() <= 750.0

@@ -235,6 +235,21 @@ def cylinder_chi(nx: int, ny: int, nz: int, ez_K: float = 21000.0) -> np.ndarray
     return (600.0 + np.where(inside, 200.0 * np.exp(-500.0 * r2), 0.0)) / ez_K
 
 
+def helix_chi(nx: int, ny: int, nz: int, ez_K: float = 21000.0) -> np.ndarray:
+    """The non-commensurate helix of the weak-scaling runs (paper Sec. 4.3,
+    Eq. case12_chi): 550 K + 200 K exp(-750 (dx^2 + dz^2)) with
+    dx = x/L - (cos(6 pi (y/L + 1))/8 - 1/16) and
+    dz = z/L - (sin(4 pi (y/L + 1))/8 - 1/16), coordinates of the cell centres
+    from the sample's centre, h = 1/nz, L = nz h; units of e_z/k_B."""
+    h = 1.0 / nz
+    zc = (np.arange(nz) + 0.5 - 0.5 * nz) * h
+    yc = (np.arange(ny) + 0.5 - 0.5 * ny) * h
+    xc = (np.arange(nx) + 0.5 - 0.5 * nx) * h
+    dx = xc[None, None, :] - (np.cos(6 * np.pi * (yc + 1)) / 8 - 1.0 / 16)[None, :, None]
+    dz = zc[:, None, None] - (np.sin(4 * np.pi * (yc + 1)) / 8 - 1.0 / 16)[None, :, None]
+    return (550.0 + 200.0 * np.exp(-750.0 * (dx * dx + dz * dz))) / ez_K
+
+
 def defect_state(nx: int, ny: int, nz: int, U: float = 1e-7) -> dict:
     """Initial (v, sigma, chi) of the single-defect run (paper Sec. 4.4): the
     sample at rest and free of stress, chi from Eq. case0_chi.  The wall speed
