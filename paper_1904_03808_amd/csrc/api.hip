@@ -682,6 +682,14 @@ bool valid_stz(const qs_stz_params* sp) {
          (sp->advect == 0 || sp->advect == 1) && (sp->chi_wall == 0 || sp->chi_wall == 1);
 }
 
+// Scratch for D^pl per cell during an STZ step: a fine-level FP64 buffer of
+// the hierarchy that holds nothing between solves (the residual of an FP64
+// handle, the second iterate buffer of an FP32-IR one; each solve rewrites
+// them before reading), nx*ny*3*(nz+1) >= nx*ny*nz doubles.
+double* stz_dcell(qs_handle* hd) {
+  return hd->p.precision == QS_FP64 ? hd->L[0].r64 : hd->L[0].xalt64;
+}
+
 StzArgs stz_args(qs_handle* hd, const qs_stz_params* sp) {
   StzArgs a;
   a.s_y = sp->s_y;
@@ -719,7 +727,8 @@ qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v, c
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !sigma_star || !chi_next) return QS_ERR_ARG;
   if (sigma_star == sigma || chi_next == chi) return QS_ERR_ARG;
   if ((sp->l_diff > 0.0 || sp->advect) && hd->L[0].d.nz < 2) return QS_ERR_SHAPE;  // ghost layers need two cells
-  launch_stz_step(v, sigma, chi, sigma_star, chi_next, hd->L[0].d, stz_args(hd, sp), hd->stream);
+  launch_stz_step(v, sigma, chi, sigma_star, chi_next, stz_dcell(hd), hd->L[0].d, stz_args(hd, sp),
+                  hd->stream);
   return launch_check();
 }
 
@@ -762,7 +771,7 @@ qs_status projection_step_impl(qs_handle* hd, const qs_stz_params* sp, double U_
   double* chi1 = cv.take<double>(cells(d));
   double* b = cv.take<double>(d.elems());
   const StzArgs a = stz_args(hd, sp);
-  launch_stz_step(v, sigma, chi, sstar, chi1, d, a, hd->stream);
+  launch_stz_step(v, sigma, chi, sstar, chi1, stz_dcell(hd), d, a, hd->stream);
   if (lo)
     launch_copy_walls(v, lo, hi, d, hd->stream);
   else
@@ -821,7 +830,7 @@ qs_status qs_explicit_step(qs_handle* hd, const qs_stz_params* sp, double U_wall
   double* vnew = cv.take<double>(d.elems());
   StzArgs a = stz_args(hd, sp);
   a.advect = 1;  // the stress equation of the explicit method carries the advection
-  launch_stz_step(v, sigma, chi, sstar, chi1, d, a, hd->stream);
+  launch_stz_step(v, sigma, chi, sstar, chi1, stz_dcell(hd), d, a, hd->stream);
   launch_explicit_velocity(v, sigma, vnew, d, hd->p.h, sp->dt, rho, kappa, hd->stream);
   launch_set_walls(vnew, d, U_wall, hd->stream);
   launch_stress_update(sstar, v, sigma, d, hd->p.h, sp->dt, hd->p.lambda, hd->p.mu, hd->stream);

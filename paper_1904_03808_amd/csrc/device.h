@@ -146,8 +146,9 @@ struct StzArgs {
   int advect; // 1: sigma* carries the advection -(v . grad) sigma (Eq. ENO)
   int chi_wall;  // 1: no chi diffusion flux through the wall faces
 };
+// dcell: device scratch of nx*ny*nz doubles, used when a.l2 > 0 (may be null otherwise)
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
-                     double* chi1, Dims d, const StzArgs& a, hipStream_t s);
+                     double* chi1, double* dcell, Dims d, const StzArgs& a, hipStream_t s);
 void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s);
 void launch_stress_update(const double* sstar, const double* v, double* out, Dims d, double h,
                           double dt, double lam, double mu, hipStream_t s);

@@ -208,7 +208,8 @@ __device__ __forceinline__ double dpl_ghost(const double* __restrict__ sigma,
 // div(D^pl grad chi) at cell c (Eq. chi_evo): flux form over the six faces,
 // face coefficient (D_c + D_n)/2, in the order y+1, y-1, x+1, x-1, z-1, z+1.
 __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__ sigma,
-                                                      const double* __restrict__ chi, int nx,
+                                                      const double* __restrict__ chi,
+                                                      const double* __restrict__ Dcell, int nx,
                                                       int ny, int nz, const CellIdx& c, int o,
                                                       double Dc, double xc, const StzArgs& a) {
   const int N = nx * ny * nz, P = nx * ny;
@@ -219,12 +220,12 @@ __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const double Dn = dpl_cell(sigma, chi, N, nb[q], a);
+    const double Dn = Dcell[nb[q]];
     s += 0.5 * (Dc + Dn) * (chi[nb[q]] - xc);
   }
   double xn, Dn;
   if (c.k > 0) {
-    Dn = dpl_cell(sigma, chi, N, o - P, a);
+    Dn = Dcell[o - P];
     xn = chi[o - P];
   } else if (a.chi_wall) {  // no flux through the wall face
     Dn = Dc;
@@ -234,7 +235,7 @@ __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__
   }
   s += 0.5 * (Dc + Dn) * (xn - xc);
   if (c.k < nz - 1) {
-    Dn = dpl_cell(sigma, chi, N, o + P, a);
+    Dn = Dcell[o + P];
     xn = chi[o + P];
   } else if (a.chi_wall) {
     Dn = Dc;
@@ -248,13 +249,23 @@ __device__ __forceinline__ double chi_flux_divergence(const double* __restrict__
 
 // DIFF: with the diffusion term of Eq. chi_evo (l > 0); each cell evaluates
 // D^pl of its six neighbours itself, from sigma and chi of step n.
+// D^pl of every cell (0 where chi is not positive), for the diffusion term.
+__global__ __launch_bounds__(256) void k_dpl_cells(const double* __restrict__ sigma,
+                                                   const double* __restrict__ chi,
+                                                   double* __restrict__ D, int N, StzArgs a) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  D[t] = dpl_cell(sigma, chi, N, t, a);
+}
+
 template <bool DIFF, bool ADV>
 __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
                                                   const double* __restrict__ sigma,
                                                   const double* __restrict__ chi,
                                                   double* __restrict__ sstar,
-                                                  double* __restrict__ chi1, int nx, int ny, int nz,
-                                                  StzArgs a) {
+                                                  double* __restrict__ chi1,
+                                                  const double* __restrict__ Dcell, int nx, int ny,
+                                                  int nz, StzArgs a) {
   CellIdx c;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (!cell_of(t, nx, ny, nz, &c)) return;
@@ -329,7 +340,7 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
   if (DIFF) {
     // the cell's own D^pl as in the flux form (0 where chi is not positive)
     const double Dc = x > 0.0 ? pl.D : 0.0;
-    xn = xn + (a.dt / a.c0) * a.l2 * chi_flux_divergence(sigma, chi, nx, ny, nz, c, t, Dc, x, a);
+    xn = xn + (a.dt / a.c0) * a.l2 * chi_flux_divergence(sigma, chi, Dcell, nx, ny, nz, c, t, Dc, x, a);
   }
   chi1[t] = xn;
 }
@@ -732,21 +743,24 @@ inline int blocks_for(long long n, int bs) { return static_cast<int>((n + bs - 1
 }  // namespace
 
 void launch_stz_step(const double* v, const double* sigma, const double* chi, double* sstar,
-                     double* chi1, Dims d, const StzArgs& a, hipStream_t s) {
+                     double* chi1, double* dcell, Dims d, const StzArgs& a, hipStream_t s) {
   const long long n = static_cast<long long>(d.nx) * d.ny * d.nz;
   const dim3 grid(blocks_for(n, 256)), block(256);
+  // the diffusion term reads D^pl of the six face neighbours: one pass first
+  if (a.l2 > 0.0)
+    hipLaunchKernelGGL(k_dpl_cells, grid, block, 0, s, sigma, chi, dcell, static_cast<int>(n), a);
   if (a.l2 > 0.0 && a.advect)
     hipLaunchKernelGGL((k_stz_step<true, true>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       d.nx, d.ny, d.nz, a);
+                       dcell, d.nx, d.ny, d.nz, a);
   else if (a.l2 > 0.0)
     hipLaunchKernelGGL((k_stz_step<true, false>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       d.nx, d.ny, d.nz, a);
+                       dcell, d.nx, d.ny, d.nz, a);
   else if (a.advect)
     hipLaunchKernelGGL((k_stz_step<false, true>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       d.nx, d.ny, d.nz, a);
+                       dcell, d.nx, d.ny, d.nz, a);
   else
     hipLaunchKernelGGL((k_stz_step<false, false>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       d.nx, d.ny, d.nz, a);
+                       dcell, d.nx, d.ny, d.nz, a);
 }
 
 void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s) {
