@@ -185,7 +185,9 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol,
  * three-point formula where the cell is more curved than its upwind
  * neighbour, centred difference otherwise); x and y wrap, and in z two ghost
  * layers continue the two nearest layers linearly (Sec. 3.5).  l > 0 or
- * advect = 1 need nz >= 2 (else QS_ERR_SHAPE).
+ * advect = 1 need nz >= 2 (else QS_ERR_SHAPE).  With l > 0, D^pl of every
+ * cell is first written into a fine-level buffer of the handle's workspace
+ * that holds nothing between solves (calls on one handle must not overlap).
  * Outputs may not alias inputs. */
 qs_status qs_stz_step(qs_handle* hd, const qs_stz_params* sp, const double* v,
                       const double* sigma, const double* chi, double* sigma_star,
