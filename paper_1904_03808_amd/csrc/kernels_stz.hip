@@ -383,32 +383,6 @@ __device__ __forceinline__ double node_diff(const double g[2][2][2], int b) {
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ sstar, double* __restrict__ b,
-                                             int nx, int ny, int nz, double scale) {
-  int i, j, k;
-  NodeCells nc;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!node_of(t, nx, ny, nz, &i, &j, &k, &nc)) return;
-  const int N = nx * ny * nz, P = nx * ny, C = (nz + 1) * P;
-  double acc[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int n = 0; n < 6; ++n) {
-    double g[2][2][2];
-#pragma unroll
-    for (int ez = 0; ez < 2; ++ez)
-#pragma unroll
-      for (int ey = 0; ey < 2; ++ey)
-#pragma unroll
-        for (int ex = 0; ex < 2; ++ex) g[ez][ey][ex] = sstar[n * N + nc.cell[ez][ey][ex]];
-    const int p = VA[n], q = VB[n];
-    acc[p] += node_diff(g, q);
-    if (p != q) acc[q] += node_diff(g, p);
-  }
-  const int o = k * P + j * nx + i;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) b[a * C + o] = acc[a] * scale;
-}
-
 // Explicit method (Sec. 3.2): the new velocity at an interior node,
 //   v' = v + dt ((D_h sigma)/rho - (v . grad) v + kappa lap v),
 // all from step n: D_h sigma as in k_rhs, the Laplacian by Eq. col_snd_deriv,
@@ -467,6 +441,54 @@ __global__ __launch_bounds__(256) void k_explicit_velocity(const double* __restr
     const double lap = (lx + ly + lz) / (h * h);
     const double acc = (div[a] * (0.25 / h)) / rho - adv + kappa * lap;
     vout[a * C + o] = g[2] + dt * acc;
+  }
+}
+
+// b = scale * D_h sigma* at the interior nodes (staggered divergence, the
+// node form of Eq. stag_stenc).  Each thread marches up a z-segment of one
+// (i, j) column: the cell plane below a node is the one above the previous
+// node, kept in registers, so every cell plane is read once per segment.
+__global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ sstar,
+                                               double* __restrict__ b, int nx, int ny, int nz,
+                                               int seg, double scale) {
+  const int P = nx * ny;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P) return;
+  const int k0 = 1 + static_cast<int>(blockIdx.y) * seg;
+  if (k0 > nz - 1) return;
+  const int k1 = min(k0 + seg, nz);  // nodes k0 .. k1-1
+  const int i = t % nx, j = t / nx;
+  const int N = P * nz, C = (nz + 1) * P;
+  const int xs[2] = {i == 0 ? nx - 1 : i - 1, i};
+  const int ys[2] = {j == 0 ? ny - 1 : j - 1, j};
+  double lo[6][2][2];
+#pragma unroll
+  for (int n = 0; n < 6; ++n)
+#pragma unroll
+    for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+      for (int ex = 0; ex < 2; ++ex)
+        lo[n][ey][ex] = sstar[n * N + ((k0 - 1) * ny + ys[ey]) * nx + xs[ex]];
+  for (int k = k0; k < k1; ++k) {
+    double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      double g[2][2][2];
+#pragma unroll
+      for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+        for (int ex = 0; ex < 2; ++ex) {
+          g[0][ey][ex] = lo[n][ey][ex];
+          g[1][ey][ex] = sstar[n * N + (k * ny + ys[ey]) * nx + xs[ex]];
+          lo[n][ey][ex] = g[1][ey][ex];
+        }
+      const int p = VA[n], q = VB[n];
+      acc[p] += node_diff(g, q);
+      if (p != q) acc[q] += node_diff(g, p);
+    }
+    const int o = k * P + j * nx + i;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) b[a * C + o] = acc[a] * scale;
   }
 }
 
@@ -764,8 +786,13 @@ void launch_stz_step(const double* v, const double* sigma, const double* chi, do
 }
 
 void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s) {
-  const long long n = static_cast<long long>(d.nx) * d.ny * (d.nz - 1);
-  hipLaunchKernelGGL(k_rhs, dim3(blocks_for(n, 256)), dim3(256), 0, s, sstar, b, d.nx, d.ny, d.nz,
+  // z-segments of 16 node planes, fewer planes when that leaves too few workgroups
+  const int P = d.nx * d.ny, interior = d.nz - 1;
+  const int wgs = static_cast<int>(blocks_for(P, 256));
+  int seg = 16;
+  while (seg > 1 && wgs * ((interior + seg - 1) / seg) < 2048) seg /= 2;
+  const int nseg = (interior + seg - 1) / seg;
+  hipLaunchKernelGGL(k_rhs, dim3(wgs, nseg), dim3(256), 0, s, sstar, b, d.nx, d.ny, d.nz, seg,
                      0.25 / (h * dt));
   hipLaunchKernelGGL(k_zero_walls, dim3(blocks_for(6LL * d.plane(), 256)), dim3(256), 0, s, b,
                      d.nx, d.ny, d.nz);
