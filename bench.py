@@ -637,6 +637,8 @@ def main():
                     help="only run one of the paper's simple-shear runs (see --paper-n, "
                          "--defect-steps) and print it")
     ap.add_argument("--paper-n", type=int, default=256, help="N of the N x N x N/2 grid")
+    ap.add_argument("--min-coarse-nz", type=int, default=4,
+                    help="coarsening limit of the paper runs (8 for N = 80: 80 x 80 x 40 halves to nz = 5)")
     ap.add_argument("--chi-wall", type=int, default=0, choices=(0, 1),
                     help="chi diffusion at the walls: 0 ghost-state D^pl, 1 the wall cell's own")
     ap.add_argument("--explicit-only", action="store_true",
@@ -668,7 +670,8 @@ def main():
     if args.paper_run:
         print(json.dumps({"paper_run": defect_run(N=args.paper_n, steps=args.defect_steps,
                                                   kind=args.paper_run, per_vcycle=False,
-                                                  chi_wall=args.chi_wall)}))
+                                                  chi_wall=args.chi_wall,
+                                                  min_coarse_nz=args.min_coarse_nz)}))
         return
     if args.explicit_only:
         print(json.dumps({"explicit_vs_qs_64x64x32": explicit_vs_qs()}))
