@@ -223,7 +223,7 @@ MAX_SUBSTEPS = 65536
 
 def substep_count(sbar, chi, dt, mu, p):
     """Sub-steps of the local plastic relaxation per cell (see stz_pointwise):
-    n_sub <= 1 gives 1 (the single forward-Euler step of Eq. sig_star_qs),
+    n_sub in {0, 1} gives 1 (the single forward-Euler step of Eq. sig_star_qs),
     n_sub > 1 gives n_sub, and n_sub = -1 gives ceil(4 mu dt dD^pl/dsbar) at
     the state of step n, between 1 and MAX_SUBSTEPS, so that each sub-step
     tau keeps tau 2 mu dD^pl/dsbar <= 1/2 (the explicit step of
@@ -249,6 +249,8 @@ def stz_pointwise(L, sigma, chi, dt, lam, mu, p):
     sub-step left: sigma* = sigma_M + dt (kinematic terms).  M = 1 is the
     single step of Eq. sig_star_qs.
     """
+    if int(p.get("n_sub", 1)) == -2:
+        return _stz_pointwise_implicit(L, sigma, chi, dt, lam, mu, p)
     if int(p.get("n_sub", 1)) not in (0, 1):
         return _stz_pointwise_substeps(L, sigma, chi, dt, lam, mu, p)
     S = voigt_to_full(sigma)
@@ -264,6 +266,48 @@ def stz_pointwise(L, sigma, chi, dt, lam, mu, p):
     # D^pl (tensor) : sigma_0 = (D^pl / sbar) sigma_0 : sigma_0 = 2 sbar D^pl
     chi_next = chi + (dt / p["c0"]) * (2.0 * sbar * Dpl / p["s_y"]) * (p["chi_inf"] - chi)
     return full_to_voigt(Sstar), chi_next
+
+
+IMPLICIT_BISECTIONS = 64
+
+
+def implicit_sbar(sbar, chi, dt, mu, p):
+    """Backward-Euler s of the local relaxation dsbar/dt = -2 mu D^pl(sbar, chi)
+    with chi held at step n: the root of g(s) = s - sbar + 2 mu dt D^pl(s, chi)
+    in [s_Y, sbar] for sbar > s_Y (g is increasing there, g(s_Y) < 0 <= g(sbar)),
+    found by IMPLICIT_BISECTIONS halvings of that interval; sbar itself at or
+    below yield."""
+    sbar = np.asarray(sbar, dtype=float)
+    act = sbar > p["s_y"]
+    lo = np.where(act, p["s_y"], sbar)
+    hi = sbar.copy()
+    for _ in range(IMPLICIT_BISECTIONS):
+        mid = 0.5 * (lo + hi)
+        g = mid - sbar + 2.0 * mu * dt * plastic_rate(mid, chi, p)
+        lo = np.where(act & (g < 0.0), mid, lo)
+        hi = np.where(act & (g >= 0.0), mid, hi)
+    return np.where(act, hi, sbar)
+
+
+def _stz_pointwise_implicit(L, sigma, chi, dt, lam, mu, p):
+    """n_sub = -2 (an extension, not the paper's): the plastic terms by
+    backward Euler.  The deviator keeps its direction and shrinks to the
+    implicit_sbar value; the pressure is kept; chi takes
+    chi' = (chi + a chi_inf) / (1 + a), a = (dt/c0) 2 s' D^pl(s', chi)/s_Y,
+    which stays between chi and chi_inf; the kinematic terms come from
+    sigma^n as in the sub-stepped form."""
+    S = voigt_to_full(sigma)
+    S0, sbar = deviator(S)
+    s1 = implicit_sbar(sbar, chi, dt, mu, p)
+    scale = np.where(sbar > p["s_y"], s1 / np.where(sbar > 0.0, sbar, 1.0), 1.0)
+    Sp = S - (1.0 - scale) * S0
+    D1 = plastic_rate(s1, chi, p)
+    a = (dt / p["c0"]) * (2.0 * s1 * D1 / p["s_y"])
+    chi_next = (chi + a * p["chi_inf"]) / (1.0 + a)
+    trL = L[0, 0] + L[1, 1] + L[2, 2]
+    kin = (np.einsum("ab...,bc...->ac...", L, S) + np.einsum("ab...,cb...->ac...", S, L)
+           - trL * S)
+    return full_to_voigt(Sp + dt * kin), chi_next
 
 
 def _stz_pointwise_substeps(L, sigma, chi, dt, lam, mu, p):

@@ -482,3 +482,44 @@ def test_chi_diffusion_closed_walls_conserve_chi():
     c = chi[:, 0, 0]
     want = (0.5 * (D[1] + D[0]) * (c[0] - c[1]) + 0.5 * (D[-2] + D[-1]) * (c[-1] - c[-2])) / h**2
     assert np.isclose(t0[:, 0, 0].sum(), want, rtol=1e-10)
+
+
+def test_implicit_plastic_update_bounds_and_consistency():
+    """n_sub = -2 (backward Euler of the local relaxation, an extension): for
+    any dt, even 1e8 t_s, sbar lands in [s_Y, sbar^n] and chi between chi^n
+    and chi_inf, with pressure and deviator direction kept; the bisection
+    solves its equation s - sbar + 2 mu dt D^pl(s) = 0 to the last bits; its
+    one-step error against scipy's Radau solution of the local ODE falls as
+    dt^2 (a consistent first-order method), as does its distance to the
+    single forward-Euler step."""
+    rng = np.random.default_rng(21)
+    vals = rng.standard_normal(6)
+    S = voigt_to_full(_uniform(1, vals))
+    _, sb = stz.deviator(S)
+    s0 = 1.4 * P["s_y"]
+    vals = vals * (s0 / float(sb.ravel()[0]))
+    chi = 0.04
+    p2 = dict(P, n_sub=-2)
+    S0n, _ = stz.deviator(voigt_to_full(_uniform(1, vals)))
+    for dt in (10.0, 1e4, 1e8):
+        T, T0, tbar, c1 = _one_cell(vals, chi, dt, p2)
+        assert P["s_y"] <= tbar <= s0 and chi <= c1 <= P["chi_inf"]
+        assert np.allclose(T0 / tbar, S0n / s0, rtol=1e-12, atol=1e-14)
+        assert np.isclose(np.trace(T).item(), np.trace(voigt_to_full(_uniform(1, vals))).item(),
+                          rtol=1e-14, atol=1e-18)
+        g = tbar - s0 + 2 * MU * dt * float(stz.plastic_rate(np.array([tbar]), np.array([chi]), P)[0])
+        slope = float(stz.plastic_rate_slope(np.array([tbar]), np.array([chi]), P)[0])
+        assert abs(g) <= 1e-14 * s0 * (1 + 2 * MU * dt * slope)
+    slope0 = float(stz.plastic_rate_slope(np.array([s0]), np.array([chi]), P)[0])
+    base = 0.05 / (2 * MU * slope0)
+    errs, gaps = [], []
+    for k in range(3):
+        dt = base / 2 ** k
+        s_ex, _ = _relaxation_exact(s0, chi, dt, P)
+        _, _, tb, _ = _one_cell(vals, chi, dt, p2)
+        _, _, tf, _ = _one_cell(vals, chi, dt, P)
+        errs.append(abs(tb - s_ex))
+        gaps.append(abs(tb - tf))
+    for e in (errs, gaps):
+        r = np.array(e[:-1]) / np.array(e[1:])
+        assert np.all(r > 3.3) and np.all(r < 4.7), e
