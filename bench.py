@@ -402,18 +402,19 @@ def defect_run(N: int = 256, steps: int = 5000, min_coarse_nz: int = 4, n_sub: i
     return res
 
 
-def weld_run(N: int = 256, steps: int = 12, both: bool = True) -> dict:
+def weld_run(N: int = 256, steps: int = 500, both: bool = True, n_sub: int = -2) -> dict:
     """Friction welding (Sec. 5) on the slender N x N x N/4 sample (h = 2L/N):
     spinning-disc wall data of Eqs. u_weld and v_weld on both walls
     (omega = 2 pi / 1e8 t_s, R = 1/3), chi from Eq. convolve with mean 450 K,
     std 15 K, l_c = 5h, l = h, dt = 2e4 t_s, the sample at rest at t = 0.
     `steps` FP32-IR projection steps (rtol 1e-10, warm-started) timed between
-    device synchronisations, the plastic terms sub-stepped per cell.  The
-    default 12 steps cover the elastic loading and the onset of yield (sbar
-    reaches 2 s_Y near the disc edges).  Later steps leave the explicit
-    scheme's reach at this dt: near step 15 the chi diffusion number
-    (dt/c0) 6 D^pl l^2/h^2 passes 1, and without diffusion the local
-    relaxation near step 38 needs more than 65536 sub-steps."""
+    device synchronisations, the plastic terms by backward Euler (n_sub = -2;
+    500 steps, a tenth of the paper's run).  The explicit forms cannot take
+    this dt once the sample flows: with per-cell sub-steps (n_sub = -1) the chi
+    diffusion number (dt/c0) 6 D^pl l^2/h^2 passes 1 near step 15, and
+    without diffusion the local relaxation near step 38 needs more than 65536
+    sub-steps; backward Euler keeps D^pl near the loading rate, which keeps the
+    diffusion number small."""
     import math
 
     import torch
@@ -424,7 +425,7 @@ def weld_run(N: int = 256, steps: int = 12, both: bool = True) -> dict:
     dev = torch.device("cuda:0")
     nx, ny, nz = N, N, N // 4
     h = 2.0 / N
-    P, dt, omega = dict(stz_constants(), l_diff=h, n_sub=-1), 2e4, 2 * math.pi / 1e8
+    P, dt, omega = dict(stz_constants(), l_diff=h, n_sub=n_sub), 2e4, 2 * math.pi / 1e8
     lo, hi = (torch.from_numpy(w).to(dev) for w in weld_walls(nx, ny, nz, omega, h, True, both))
     c0 = torch.from_numpy(chi_field(nx, ny, nz, 5, 450.0 / 21000, 15.0 / 21000, 5.0)).to(dev)
     g = MGSolver(nx, ny, nz, h, lam, mu, min_coarse_nz=4, precision="fp32-ir", device=dev)
@@ -447,7 +448,9 @@ def weld_run(N: int = 256, steps: int = 12, both: bool = True) -> dict:
            "max_vcycles_in_a_step": max(cycles), "walls": "both" if both else "top",
            "state_at_end": {"t_end": steps * dt,
                             "sbar_max_over_sY": (sbar.max() / P["s_y"]).item()},
-           "solver": "fp32-ir, rtol 1e-10", "plastic_substeps": "per cell from the stability bound",
+           "solver": "fp32-ir, rtol 1e-10",
+           "plastic_update": ("backward Euler" if n_sub == -2 else
+                              "per-cell sub-steps" if n_sub == -1 else "n_sub = %d" % n_sub),
            "inputs": "chi Eq. convolve (450 K, 15 K, l_c = 5h, seed 5), sigma = 0, v = 0 at t = 0; "
                      "l = h, dt = 2e4 t_s, omega = 2 pi / 1e8 t_s, R = 1/3"}
     g.close()

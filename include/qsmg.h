@@ -177,7 +177,12 @@ qs_status qs_mg_solve(qs_handle* hd, const double* b, double* x, double rtol,
  * then sigma* = sigma_M + dt (L sigma + sigma L^T - tr(L) sigma) with sigma
  * of step n, and chi' = chi_M + the diffusion term above.  For n_sub = -1 each
  * sub-step keeps (dt/M) 2 mu dD^pl/dsbar <= 1/2 at the start state, below the
- * explicit step's stability limit of 2.  Other n_sub < -1: QS_ERR_ARG.
+ * explicit step's stability limit of 2.  n_sub = -2 takes the plastic
+ * terms by backward Euler instead (an extension, stable for any dt): with chi
+ * held at step n, sbar' is the root of s - sbar + 2 mu dt D^pl(s, chi) in
+ * [s_y, sbar] (64 bisections), the deviator shrinks by sbar'/sbar, the
+ * pressure is kept, and chi_M = (chi + c chi_inf)/(1 + c) with
+ * c = (dt/c0) 2 sbar' D^pl(sbar', chi) / s_y.  n_sub < -2: QS_ERR_ARG.
  * Advection (advect = 1; the stress equation of Eq. sig_star_evol carries it,
  * the quasi-static Eq. sig_star_qs leaves it out): sigma* -= dt (u . grad)
  * sigma with sigma and v of step n, u the mean of the cell's eight corner

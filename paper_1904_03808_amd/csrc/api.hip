@@ -678,7 +678,7 @@ namespace {
 
 bool valid_stz(const qs_stz_params* sp) {
   return sp && sp->tau0 > 0.0 && sp->s_y > 0.0 && sp->c0 > 0.0 && std::isfinite(sp->dt) &&
-         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff) && sp->n_sub >= -1 &&
+         sp->l_diff >= 0.0 && std::isfinite(sp->l_diff) && sp->n_sub >= -2 &&
          (sp->advect == 0 || sp->advect == 1) && (sp->chi_wall == 0 || sp->chi_wall == 1);
 }
 

@@ -142,7 +142,7 @@ struct StzArgs {
   double s_y, tau0, beta, delta_over_T, c0, chi_inf, dt;
   double lam, mu, h;
   double l2;  // squared diffusion length of Eq. chi_evo (0: no diffusion term)
-  int n_sub;  // plastic sub-steps: 1 single step, > 1 fixed count, -1 per cell
+  int n_sub;  // plastic sub-steps: 1 single step, > 1 fixed count, -1 per cell, -2 backward Euler
   int advect; // 1: sigma* carries the advection -(v . grad) sigma (Eq. ENO)
   int chi_wall;  // 1: no chi diffusion flux through the wall faces
 };

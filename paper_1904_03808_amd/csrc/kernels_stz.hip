@@ -160,6 +160,7 @@ __device__ __forceinline__ double plastic_D(double sbar, double chi, const StzAr
 }
 
 constexpr int kMaxSubsteps = 65536;
+constexpr int kImplicitBisections = 64;
 
 __device__ __forceinline__ void deviator(const double S[3][3], double S0[3][3], double* sbar) {
   const double pr = (S[0][0] + S[1][1] + S[2][2]) * (1.0 / 3.0);
@@ -298,6 +299,40 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
       sstar[n * N + t] = val;
     }
     xn = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
+  } else if (a.n_sub == -2) {
+    // backward Euler of the local relaxation, chi held at step n: the root of
+    // s - sbar + 2 mu dt D^pl(s) in [s_Y, sbar] by bisection; the deviator
+    // shrinks to it, chi' = (chi + c chi_inf) / (1 + c)
+    double s1 = sbar;
+    if (sbar > a.s_y) {
+      double lo = a.s_y, hi = sbar;
+      for (int it = 0; it < kImplicitBisections; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double g = mid - sbar + 2.0 * a.mu * a.dt * plastic_D(mid, x, a);
+        if (g < 0.0)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      s1 = hi;
+    }
+    const double scale = sbar > a.s_y ? s1 / (sbar > 0.0 ? sbar : 1.0) : 1.0;
+    const double D1 = plastic_D(s1, x, a);
+    const double cg = (a.dt / a.c0) * (2.0 * s1 * D1 / a.s_y);
+    xn = (x + cg * a.chi_inf) / (1.0 + cg);
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+      const int p = VA[n], q = VB[n];
+      double LS = 0.0, SLt = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        LS += L[p][m] * S[m][q];
+        SLt += S[p][m] * L[q][m];
+      }
+      double val = (S[p][q] - (1.0 - scale) * S0[p][q]) + a.dt * (LS + SLt - trL * S[p][q]);
+      if (ADV) val = val - a.dt * eno_advection(sigma + n * N, nx, ny, nz, c, t, u, a.h);
+      sstar[n * N + t] = val;
+    }
   } else {
     // sub-steps of the plastic terms from the state of step n
     int M = a.n_sub;

@@ -99,11 +99,12 @@ def test_stz_step_with_chi_diffusion(n):
 
 
 @pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20)])
-@pytest.mark.parametrize("n_sub,dt", [(4, 10.0), (-1, 10.0), (-1, 40.0)])
+@pytest.mark.parametrize("n_sub,dt", [(4, 10.0), (-1, 10.0), (-1, 40.0), (-2, 10.0), (-2, 1e4)])
 def test_stz_step_with_plastic_substeps(n, n_sub, dt):
     """Sub-stepped plastic terms, a fixed count and the per-cell count from
     the stability bound (up to about 40 and 150 sub-steps in these states),
-    match the oracle's."""
+    and the backward-Euler update (n_sub = -2, also at dt = 1e4 where every
+    explicit form fails), match the oracle's."""
     rng = np.random.default_rng(4)
     nx, ny, nz = n
     h = 1.0 / nz
@@ -152,14 +153,14 @@ def test_stz_step_with_advection(n):
 
 
 def test_substep_arguments():
-    """n_sub below -1 is refused, and so is any n_sub > 1 in reverse mode."""
+    """n_sub below -2 is refused, and so is any n_sub > 1 in reverse mode."""
     from paper_1904_03808_amd._capi import QSError
     nx, ny, nz = 8, 8, 8
     rng = np.random.default_rng(2)
     g = solver(nx, ny, nz)
     v, sig, chi = random_state(rng, nx, ny, nz)
     with pytest.raises(QSError):
-        g.stz_step(dict(P, n_sub=-2), 1.0, dev(v), dev(sig), dev(chi))
+        g.stz_step(dict(P, n_sub=-3), 1.0, dev(v), dev(sig), dev(chi))
     z = lambda *s: torch.zeros(s, dtype=torch.float64, device="cuda")
     with pytest.raises(QSError):
         g.stz_step_vjp(dict(P, n_sub=2), 1.0, dev(v), dev(sig), dev(chi), z(6, nz, ny, nx),
