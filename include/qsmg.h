@@ -105,8 +105,9 @@ typedef struct {
   double l_diff;           /* diffusion length l of Eq. chi_evo (units of L);
                               0 leaves the diffusion term out; the reverse-mode
                               entry points require 0                          */
-  int n_sub;               /* sub-steps of the plastic terms (qs_stz_step);
-                              0 or 1: the single step of Eq. sig_star_qs; the
+  int n_sub;               /* plastic terms of qs_stz_step: 0 or 1, the single
+                              step of Eq. sig_star_qs; M > 1, M sub-steps;
+                              -1, a per-cell count; -2, backward Euler; the
                               reverse-mode entry points require 0 or 1        */
   int advect;              /* 0 (Eq. sig_star_qs) or 1: sigma* also carries
                               -dt (v . grad) sigma (qs_stz_step); the reverse-
