@@ -523,3 +523,42 @@ def test_implicit_plastic_update_bounds_and_consistency():
     for e in (errs, gaps):
         r = np.array(e[:-1]) / np.array(e[1:])
         assert np.all(r > 3.3) and np.all(r < 4.7), e
+
+
+@pytest.mark.slow
+def test_explicit_method_reaches_the_quasi_static_state():
+    """The explicit method (Sec. 3.2) and the quasi-static method (Sec. 3.3)
+    discretise the same equations, the first with inertia and damping: on an
+    elastic simple shear whose wall speed ramps up over one t_s (Eq. u_bc) and
+    then holds, both must give the linear shear profile once the waves have
+    died out (here at t = 6 t_s on 8^3 with kappa = 4.8 h).  The stress means
+    then differ only by the quasi-static step's first-order time error:
+    each of its steps adds dt C : D at the end of the step, which is
+    mu U dt ahead of the continuous integral while U ramps, so the gap halves
+    with dt."""
+    from workloads import shear_velocity as sv
+    n = 8
+    h, UB, T = 1.0 / n, 1e-3, 6.0
+    chi = np.full((n, n, n), 0.02)  # far below any plastic activity
+    dt = h * h / 20
+    v = sv(n, n, n, 0.0)
+    s = np.zeros((6, n, n, n))
+    c = chi.copy()
+    for i in range(int(round(T / dt))):
+        U = UB * min((i + 1) * dt, 1.0)
+        v, s, c = stz.explicit_step(v, s, c, h, dt, LAM, MU, P, U, MU, 4.8 * h)
+    o = MGOracle(n, n, n, h, LAM, MU, min_coarse_nz=4)
+    gaps = []
+    for dq in (0.25, 0.125):
+        vq = sv(n, n, n, 0.0)
+        sq = np.zeros((6, n, n, n))
+        cq = chi.copy()
+        for i in range(int(round(T / dq))):
+            U = UB * min((i + 1) * dq, 1.0)
+            vq, sq, cq, _ = stz.projection_step(vq, sq, cq, h, dq, LAM, MU, P, U, o, rtol=1e-12)
+        assert np.abs(v - vq).max() <= 1e-4 * UB
+        assert np.abs(sq[4] - sq[4].mean()).max() <= 1e-12 * sq[4].mean()
+        gaps.append(sq[4].mean() - s[4].mean())
+        assert abs(gaps[-1] - MU * UB * dq) <= 0.05 * MU * UB * dq
+    # the explicit stress is uniform too: the waves are gone
+    assert np.abs(s[4] - s[4].mean()).max() <= 1e-3 * s[4].mean()
