@@ -42,6 +42,17 @@ SWEEP_COUNTERS = {
 }
 
 
+def _block(fn):
+    """Run one of the secondary measurement blocks; if it raises, report the
+    error in its place so that the main line still prints."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 - reported in the JSON line
+        import torch
+        torch.cuda.empty_cache()
+        return {"error": "%s: %s" % (type(e).__name__, e)}
+
+
 def _events_ms(fn, reps: int) -> float:
     import torch
     start = torch.cuda.Event(enable_timing=True)
@@ -772,17 +783,17 @@ def main():
                                      if traffic else None)},
     }
     if not args.no_512 and n == 256:
-        out["config2_512"] = config_512()
+        out["config2_512"] = _block(config_512)
     if not args.no_steps and n == 256:
-        out["config3_shear_256"] = config3_shear()
-        out["config4_adjoint_96"] = config4_adjoint()
+        out["config3_shear_256"] = _block(config3_shear)
+        out["config4_adjoint_96"] = _block(config4_adjoint)
     if not args.no_defect and n == 256:
-        out["defect_256x256x128"] = defect_run(steps=args.defect_steps)
+        out["defect_256x256x128"] = _block(lambda: defect_run(steps=args.defect_steps))
     if not args.no_defect and n == 256:
-        out["weld_256x256x64"] = weld_run()
-        out["explicit_vs_qs_64x64x32"] = explicit_vs_qs()
+        out["weld_256x256x64"] = _block(weld_run)
+        out["explicit_vs_qs_64x64x32"] = _block(explicit_vs_qs)
     if not args.no_table3 and n == 256:
-        out["table3_shapes"] = table3_shapes()
+        out["table3_shapes"] = _block(table3_shapes)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, results["fp64"]["cycles"])
     print(json.dumps(out))
