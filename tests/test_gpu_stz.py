@@ -124,8 +124,8 @@ def test_stz_step_with_plastic_substeps(n, n_sub, dt):
 def test_stz_step_with_advection(n):
     """The advection term -(v . grad) sigma with Eq. ENO (x, y wrap, two
     extrapolated ghost layers in z; nz = 2 puts both walls' ghosts into every
-    stencil) matches the oracle's, alone and together with chi diffusion and
-    per-cell plastic sub-steps; the curvature tests that pick each branch are
+    stencil) matches the oracle's, alone, together with chi diffusion and
+    per-cell plastic sub-steps, and with the backward-Euler update; the curvature tests that pick each branch are
     taken on identical FP64 values on both sides."""
     rng = np.random.default_rng(6)
     nx, ny, nz = n
@@ -133,7 +133,7 @@ def test_stz_step_with_advection(n):
     g = solver(nx, ny, nz)
     v, sig, chi = random_state(rng, nx, ny, nz)
     dt = 10.0
-    for extra in ({}, {"l_diff": h, "n_sub": -1}):
+    for extra in ({}, {"l_diff": h, "n_sub": -1}, {"n_sub": -2}):
         p = dict(P, advect=1, **extra)
         ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
         rs, rc = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
