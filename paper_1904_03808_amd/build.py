@@ -27,21 +27,27 @@ def _run(cmd):
 
 
 def build_library(verbose: bool = False) -> str:
+    """Compile every source (in parallel, one process per file) and link."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-    objs = []
+    jobs = []
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run(["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, src),
-              "-I", INCLUDE, "-o", obj])
-        objs.append(obj)
+        jobs.append((obj, ["g++", "-O3", "-std=c++17", "-fPIC", "-Wall", "-c",
+                           os.path.join(CSRC, src), "-I", INCLUDE, "-o", obj]))
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        r = _run([hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-I", INCLUDE,
-                                        "-I", CSRC, "-o", obj])
-        if verbose and r.stderr:
-            print(r.stderr)
-        objs.append(obj)
+        jobs.append((obj, [hipcc] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-I", INCLUDE,
+                                                 "-I", CSRC, "-o", obj]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        results = list(ex.map(lambda j: _run(j[1]), jobs))
+    if verbose:
+        for r in results:
+            if r.stderr:
+                print(r.stderr)
+    objs = [j[0] for j in jobs]
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -1,7 +1,10 @@
 """Torch-facing binding of libqsmg (names follow include/qsmg.h).
 
 Argument marshalling only: shapes and dtypes are checked here, and every
-computation runs in the HIP library on the caller's current HIP stream.
+computation runs in the HIP library.  The library's handle is bound to one
+HIP stream, torch's current stream when the MGSolver is constructed; every
+later call checks that this is still torch's current stream and raises
+otherwise, so library work is always ordered with the caller's tensor work.
 Tensors are float64, contiguous and on the GPU.
 
   MGSolver            qs_setup / qs_destroy handle with its device workspace
@@ -75,7 +78,7 @@ class MGSolver:
         hd = C.c_void_p()
         check(self._lib.qs_setup(C.byref(self._params), C.c_void_p(base), n.value,
                                  C.c_void_p(self.stream.cuda_stream), C.byref(hd)), "qs_setup")
-        self._h = hd
+        self._hd_raw = hd
         nl = C.c_int()
         self._lib.qs_level_dims(C.byref(self._params), 0, C.byref(nl), None, None, None)
         self.levels = nl.value
@@ -111,10 +114,20 @@ class MGSolver:
             self._scratch = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
         return (self._scratch.data_ptr() + 255) & ~255
 
+    @property
+    def _h(self):
+        """The library handle, after checking that torch's current stream is
+        the one the handle was set up on."""
+        hd = self.__dict__.get("_hd_raw")
+        if hd is not None and torch.cuda.current_stream(self.device).cuda_stream != self.stream.cuda_stream:
+            raise RuntimeError("MGSolver is bound to the stream that was current at construction; "
+                               "call it under that stream (torch.cuda.stream(solver.stream))")
+        return hd
+
     def close(self):
-        if getattr(self, "_h", None):
-            self._lib.qs_destroy(self._h)
-            self._h = None
+        if self.__dict__.get("_hd_raw"):
+            self._lib.qs_destroy(self._hd_raw)
+            self._hd_raw = None
 
     def __del__(self):
         try:

@@ -320,3 +320,20 @@ def test_single_level_direct():
     assert info.cycles == 1
     xr = direct_solve(b, x0, 1.0 / n, LAM, MU)
     assert rel(host(xd), xr) < 1e-12
+
+
+def test_calls_under_another_stream_are_refused():
+    """The handle is bound to the stream current at construction: a call made
+    while another torch stream is current raises instead of running unordered
+    with the caller's work; under the bound stream it runs."""
+    g, _ = make(16, 16, 16)
+    b = dev(div_node(stress_field(16, 16, 16, 0), 1.0 / 16))
+    x = torch.zeros_like(b)
+    other = torch.cuda.Stream()
+    with torch.cuda.stream(other):
+        with pytest.raises(RuntimeError, match="stream"):
+            g.solve(b, x, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert not x.any()
+    with torch.cuda.stream(g.stream):
+        assert g.solve(b, x, rtol=1e-10).converged
