@@ -215,6 +215,27 @@ qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wa
                              double* v, double* sigma, double* chi, void* scratch,
                              double rtol, int max_cycles, qs_solve_info* info);
 
+/* The same step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the step scratch comes from a fixed device array of the library instead of
+ * a `scratch` argument.  Each GPU the library runs on holds that array
+ * (QS_NOALLOC_SCRATCH_BYTES) until the process ends; its device address is
+ * resolved for the current device in qs_setup.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); the caller still
+ * passes v, sigma and chi.  Grids whose step scratch,
+ * (7 nx ny nz + 3 (nz+1) ny nx) doubles plus alignment (qs_step_scratch_bytes),
+ * exceeds QS_NOALLOC_SCRATCH_BYTES are refused with QS_ERR_SHAPE (96 MiB holds
+ * 96^3 or 128 x 128 x 64; not 128^3).  Every call on one GPU shares the array
+ * and leaves its contents behind; each call writes all of it that it reads,
+ * so nothing carries over between calls.  Calls that overlap on one GPU (on
+ * any handles or streams) race on the array and must not be made.
+ * QS_ERR_HIP if the array's address could not be resolved at setup.
+ * Otherwise arguments, results and errors as qs_projection_step. */
+#define QS_NOALLOC_SCRATCH_BYTES (96u * 1024u * 1024u)
+qs_status qs_projection_step_noalloc(qs_handle* hd, const qs_stz_params* sp, double U_wall,
+                                     double* v, double* sigma, double* chi, double rtol,
+                                     int max_cycles, qs_solve_info* info);
+
 /* The same step with wall velocities given node by node, for boundary data
  * that varies in x and y, such as the spinning discs of the friction-welding
  * runs (Sec. 5, Eqs. u_weld and v_weld): the planes k = 0 and k = nz of

@@ -21,6 +21,7 @@ QS_ERR_WORKSPACE = -6
 QS_FP64 = 0
 QS_FP32_IR = 1
 QS_HIST = 64
+QS_NOALLOC_SCRATCH_BYTES = 96 * 1024 * 1024
 
 
 class QSParams(C.Structure):
@@ -67,6 +68,8 @@ SIGNATURES = {
     "qs_step_scratch_bytes": [_P, C.POINTER(C.c_size_t)],
     "qs_projection_step": [_P, C.POINTER(QSStzParams), _D, _P, _P, _P, _P, _D, _I,
                            C.POINTER(QSSolveInfo)],
+    "qs_projection_step_noalloc": [_P, C.POINTER(QSStzParams), _D, _P, _P, _P, _D, _I,
+                                   C.POINTER(QSSolveInfo)],
     "qs_projection_step_walls": [_P, C.POINTER(QSStzParams), _P, _P, _P, _P, _P, _P, _D, _I,
                                  C.POINTER(QSSolveInfo)],
     "qs_explicit_step": [_P, C.POINTER(QSStzParams), _D, _D, _D, _P, _P, _P, _P],

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -97,6 +98,7 @@ struct qs_handle {
   double* pinned_dev = nullptr;  // the same memory as the device addresses it (null: copy instead)
   bool row_sweep = false;    // colour order allows the row-parity sweep kernel
   size_t lds_limit = 0;      // bytes of LDS a workgroup may use
+  void* static_scratch = nullptr;  // device address of `scratch` on this handle's device (or null)
 };
 
 namespace {
@@ -246,12 +248,12 @@ void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_inte
 // level carries wall data; coarse levels and the FP32 correction equation
 // have zero walls, and b is used directly.
 template <typename T>
-void coarse_solve(qs_handle* hd, int l, T* x, const T* b, T* scratch) {
+void coarse_solve(qs_handle* hd, int l, T* x, const T* b, T* tmp) {
   LevelBufs& lb = hd->L[l];
   const T* rhs = b;
   if (l == 0 && sizeof(T) == sizeof(double)) {
-    residual<T>(hd, l, x, b, scratch, true);
-    rhs = scratch;
+    residual<T>(hd, l, x, b, tmp, true);
+    rhs = tmp;
   }
   launch_coarse_solve<T>(hd->Ainv, hd->ncoarse, rhs, x, lb.d, hd->ctin, hd->ctout, hd->stream);
 }
@@ -378,6 +380,42 @@ double pow2_near(double v) {
   return std::ldexp(1.0, static_cast<int>(std::lround(std::log2(v))));
 }
 
+// Step scratch for callers that cannot allocate (qs_projection_step_noalloc):
+// a fixed device array of QS_NOALLOC_SCRATCH_BYTES that every GPU the library
+// runs on holds until the process ends.  Host code never passes `scratch`
+// itself to a kernel or copy (on the host it is only a stand-in for the
+// symbol); it uses the device address resolved per device at setup.
+static __device__ __align__(256) unsigned char scratch[QS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_addr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per
+// device (null, with the reason in the last-error text, if that failed).
+void* static_scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_tried[dev]) {
+    g_scratch_tried[dev] = true;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) {
+      g_scratch_addr[dev] = ptr;
+    } else {
+      (void)hipGetLastError();
+      std::snprintf(g_last_error, sizeof(g_last_error), "hipGetSymbolAddress(scratch): %s",
+                    hipGetErrorString(e));
+    }
+  }
+  return g_scratch_addr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -435,6 +473,7 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
   if (!hd) return QS_ERR_ARG;
   hd->p = *p;
   hd->stream = static_cast<hipStream_t>(stream);
+  hd->static_scratch = static_scratch_address();
   carve(p, dims, static_cast<char*>(workspace), hd, &need);
   {
     const hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&hd->pinned), 4 * sizeof(double));
@@ -758,15 +797,17 @@ namespace {
 // lo is null, else copied from lo and hi.
 qs_status projection_step_impl(qs_handle* hd, const qs_stz_params* sp, double U_wall,
                                const double* lo, const double* hi, double* v, double* sigma,
-                               double* chi, void* scratch, double rtol, int max_cycles,
+                               double* chi, void* step_buf, double rtol, int max_cycles,
                                qs_solve_info* info) {
-  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || max_cycles < 0 ||
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !step_buf || max_cycles < 0 ||
       !aligned16(v))
     return QS_ERR_ARG;
-  if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(step_buf) & 255) return QS_ERR_WORKSPACE;
   const Dims d = hd->L[0].d;
   if ((sp->l_diff > 0.0 || sp->advect) && d.nz < 2) return QS_ERR_SHAPE;
-  Carver cv{static_cast<char*>(scratch)};
+  // every piece is written in full before it is read (sigma*, chi' by the STZ
+  // step, b with its wall planes by the RHS), so nothing needs clearing
+  Carver cv{static_cast<char*>(step_buf)};
   double* sstar = cv.take<double>(6 * cells(d));
   double* chi1 = cv.take<double>(cells(d));
   double* b = cv.take<double>(d.elems());
@@ -790,15 +831,32 @@ qs_status projection_step_impl(qs_handle* hd, const qs_stz_params* sp, double U_
 }  // namespace
 
 qs_status qs_projection_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double* v,
-                             double* sigma, double* chi, void* scratch, double rtol,
+                             double* sigma, double* chi, void* step_buf, double rtol,
                              int max_cycles, qs_solve_info* info) {
-  return projection_step_impl(hd, sp, U_wall, nullptr, nullptr, v, sigma, chi, scratch, rtol,
+  return projection_step_impl(hd, sp, U_wall, nullptr, nullptr, v, sigma, chi, step_buf, rtol,
                               max_cycles, info);
+}
+
+qs_status qs_projection_step_noalloc(qs_handle* hd, const qs_stz_params* sp, double U_wall,
+                                     double* v, double* sigma, double* chi, double rtol,
+                                     int max_cycles, qs_solve_info* info) {
+  if (!hd) return QS_ERR_ARG;
+  const size_t need = step_scratch(hd);
+  if (need > QS_NOALLOC_SCRATCH_BYTES) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "qs_projection_step_noalloc: the grid needs %zu bytes of step scratch, the "
+                  "static buffer holds %zu",
+                  need, static_cast<size_t>(QS_NOALLOC_SCRATCH_BYTES));
+    return QS_ERR_SHAPE;
+  }
+  if (!hd->static_scratch) return QS_ERR_HIP;  // symbol address not resolved at setup
+  return projection_step_impl(hd, sp, U_wall, nullptr, nullptr, v, sigma, chi,
+                              hd->static_scratch, rtol, max_cycles, info);
 }
 
 qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp, const double* wall_lo,
                                    const double* wall_hi, double* v, double* sigma, double* chi,
-                                   void* scratch, double rtol, int max_cycles,
+                                   void* step_buf, double rtol, int max_cycles,
                                    qs_solve_info* info) {
   if (!wall_lo || !wall_hi) return QS_ERR_ARG;
   if (hd) {
@@ -812,19 +870,19 @@ qs_status qs_projection_step_walls(qs_handle* hd, const qs_stz_params* sp, const
       if (v && w0 < v1 && w0 + wb > v0) return QS_ERR_ARG;
     }
   }
-  return projection_step_impl(hd, sp, 0.0, wall_lo, wall_hi, v, sigma, chi, scratch, rtol,
+  return projection_step_impl(hd, sp, 0.0, wall_lo, wall_hi, v, sigma, chi, step_buf, rtol,
                               max_cycles, info);
 }
 
 qs_status qs_explicit_step(qs_handle* hd, const qs_stz_params* sp, double U_wall, double rho,
-                           double kappa, double* v, double* sigma, double* chi, void* scratch) {
-  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !scratch || !(rho > 0.0) ||
+                           double kappa, double* v, double* sigma, double* chi, void* step_buf) {
+  if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !step_buf || !(rho > 0.0) ||
       !std::isfinite(rho) || !(kappa >= 0.0) || !std::isfinite(kappa) || !std::isfinite(U_wall))
     return QS_ERR_ARG;
-  if (reinterpret_cast<uintptr_t>(scratch) & 255) return QS_ERR_WORKSPACE;
+  if (reinterpret_cast<uintptr_t>(step_buf) & 255) return QS_ERR_WORKSPACE;
   const Dims d = hd->L[0].d;
   if (d.nz < 2) return QS_ERR_SHAPE;
-  Carver cv{static_cast<char*>(scratch)};
+  Carver cv{static_cast<char*>(step_buf)};
   double* sstar = cv.take<double>(6 * cells(d));
   double* chi1 = cv.take<double>(cells(d));
   double* vnew = cv.take<double>(d.elems());
@@ -842,14 +900,14 @@ qs_status qs_explicit_step(qs_handle* hd, const qs_stz_params* sp, double U_wall
 qs_status qs_stz_step_vjp(qs_handle* hd, const qs_stz_params* sp, const double* v,
                           const double* sigma, const double* chi, const double* g_sstar,
                           const double* g_chi1, double* g_sigma, double* g_chi, double* g_v,
-                          void* scratch) {
+                          void* step_buf) {
   if (!hd || !valid_stz(sp) || !v || !sigma || !chi || !g_sstar || !g_chi1 || !g_sigma || !g_chi ||
-      !g_v || !scratch || sp->l_diff != 0.0 || sp->n_sub > 1 || sp->n_sub < 0 || sp->advect)
+      !g_v || !step_buf || sp->l_diff != 0.0 || sp->n_sub > 1 || sp->n_sub < 0 || sp->advect)
     return QS_ERR_ARG;
   const Dims d = hd->L[0].d;
   // the velocity-gradient cotangent is stored as [9][cells] with 32-bit indices
   if (9LL * cells(d) >= (1LL << 31)) return QS_ERR_SHAPE;
-  double* gL = static_cast<double*>(scratch);
+  double* gL = static_cast<double*>(step_buf);
   const StzArgs a = stz_args(hd, sp);
   launch_stz_step_vjp(v, sigma, chi, g_sstar, g_chi1, g_sigma, g_chi, gL, d, a, hd->stream);
   launch_grad_transpose_add(gL, g_v, d, hd->p.h, 1.0, hd->stream);

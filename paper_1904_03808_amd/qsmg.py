@@ -14,6 +14,7 @@ Tensors are float64, contiguous and on the GPU.
     .rhs              qs_rhs
     .stress_update    qs_stress_update
     .projection_step  qs_projection_step
+    .projection_step_noalloc  qs_projection_step_noalloc
     .stz_step_vjp / .rhs_vjp / .stress_update_vjp
     .level_*          test-facing pieces of the V-cycle
 """
@@ -191,6 +192,22 @@ class MGSolver:
                                           self._chk(chi, cs, "chi"), C.c_void_p(self._scratch_buf()),
                                           float(rtol), int(max_cycles), C.byref(info))
         check(st, "qs_projection_step")
+        n = min(info.cycles + 1, _capi.QS_HIST)
+        return SolveInfo(st, info.cycles, info.levels, info.rel_res, list(info.rel_res_hist[:n]))
+
+    def projection_step_noalloc(self, params: dict, dt: float, U: float, v, sigma, chi,
+                                rtol: float = 1e-10, max_cycles: int = 100) -> SolveInfo:
+        """projection_step with the library's fixed device scratch instead of
+        a scratch tensor (qs_projection_step_noalloc: nothing is allocated)."""
+        cs = self.cell_shape
+        sp = _stz(params, dt)
+        info = QSSolveInfo()
+        st = self._lib.qs_projection_step_noalloc(self._h, C.byref(sp), float(U),
+                                                  self._chk(v, self.node_shape(), "v"),
+                                                  self._chk(sigma, (6,) + cs, "sigma"),
+                                                  self._chk(chi, cs, "chi"), float(rtol),
+                                                  int(max_cycles), C.byref(info))
+        check(st, "qs_projection_step_noalloc")
         n = min(info.cycles + 1, _capi.QS_HIST)
         return SolveInfo(st, info.cycles, info.levels, info.rel_res, list(info.rel_res_hist[:n]))
 
