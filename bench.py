@@ -122,6 +122,25 @@ def cpu_baseline(sig_host, n: int, cycles_full: int) -> dict:
             "host_cpu": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
+def error_vs_oracle(n: int, sols: dict) -> dict:
+    """Relative L2 difference of each GPU solution from the FP64 oracle's
+    solution of the same system (solved to 1e-12), over the 4096 interior
+    nodes stored in tests/golden/solve256.json by an oracle-only script."""
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "solve%d.json" % n)
+    if not os.path.exists(path):
+        return {"error": "no stored oracle solution for n = %d" % n}
+    with open(path) as f:
+        ref = json.load(f)
+    out = {"oracle_rtol": ref["rtol"], "oracle_cycles": ref["cycles"], "nodes_sampled": len(ref["sample_index"])}
+    for name, x in sols.items():
+        idx = torch.tensor(ref["sample_index"], device=x.device)
+        got = x[:, idx[:, 0], idx[:, 1], idx[:, 2]].T
+        want = torch.tensor(ref["sample_x"], dtype=torch.float64, device=x.device)
+        out[name] = (torch.linalg.vector_norm(got - want) / torch.linalg.vector_norm(want)).item()
+    return out
+
+
 def smoother_timing(g, b, dtype, bytes_per_node: float) -> dict:
     """Fine-level full sweeps of solver g on its own: HIP events on the
     library's stream; the difference of a 5-sweep and a 1-sweep call leaves 4
@@ -619,6 +638,34 @@ def profile_solve(n: int) -> None:
     print(json.dumps({"profiled": "fp32-ir solve", "cycles": 2}), flush=True)
 
 
+def profile_step(n: int) -> None:
+    """Kernels for hardware-counter runs of the projection step's cell kernels
+    at n^3 (shear state, chi seed 3, dt = 10 t_s): the STZ step plain, with
+    the stress advection, and with advection and chi diffusion (l = h), then
+    the right-hand side and the stress correction, each called twice."""
+    import torch
+
+    from paper_1904_03808_amd.qsmg import MGSolver
+    from workloads import lame, shear_state, stz_constants
+    lam, mu = lame()
+    P = stz_constants()
+    st = shear_state(n, n, n, seed=3, U=1e-5)
+    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp32-ir", device="cuda:0")
+    v, s, c = (torch.from_numpy(st[k]).to("cuda:0") for k in ("v", "sigma", "chi"))
+    del st
+    for name, p in (("plain", P), ("advect", dict(P, advect=1)),
+                    ("advect+diffusion", dict(P, advect=1, l_diff=1.0 / n))):
+        for _ in range(2):
+            sstar, _ = g.stz_step(p, 10.0, v, s, c)
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "stz_step " + name}), flush=True)
+    for _ in range(2):
+        b = g.rhs(sstar, 10.0)
+        g.stress_update(sstar, v, 10.0)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": "rhs, stress_update"}), flush=True)
+
+
 def profile_smoother(n: int) -> None:
     """Kernels for hardware-counter runs: one device-to-device copy of a known
     size (calibrates FETCH_SIZE / WRITE_SIZE), then 3 fine-level sweeps in FP32
@@ -682,6 +729,8 @@ def main():
                     help="only run two FP32-IR V-cycles (for rocprofv3 counters)")
     ap.add_argument("--profile-smoother", action="store_true",
                     help="only run a calibration copy and fine-level sweeps (for rocprofv3 counters)")
+    ap.add_argument("--profile-step", action="store_true",
+                    help="only run the projection step's cell kernels (for rocprofv3 counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -699,6 +748,9 @@ def main():
         return
     if args.profile_solve:
         profile_solve(args.n)
+        return
+    if args.profile_step:
+        profile_step(args.n)
         return
     if args.paper_run:
         print(json.dumps({"paper_run": defect_run(N=args.paper_n, steps=args.defect_steps,
@@ -750,6 +802,7 @@ def main():
         results[name + "_x"] = x.clone()
     err = (torch.linalg.vector_norm(results["fp32_ir_x"] - results["fp64_x"])
            / torch.linalg.vector_norm(results["fp64_x"])).item()
+    vs_oracle = _block(lambda: error_vs_oracle(n, {k: results[k + "_x"] for k in ("fp32_ir", "fp64")}))
     del results["fp32_ir_x"], results["fp64_x"]
 
     # smoother on its own: fine level, full sweeps, HIP events on the same stream
@@ -791,6 +844,7 @@ def main():
         "fp64": results["fp64"],
         "speedup_fp32ir_vs_fp64": results["fp64"]["ms_per_solve"] / results["fp32_ir"]["ms_per_solve"],
         "fp32ir_vs_fp64_rel_l2": err,
+        "error_vs_fp64_oracle": vs_oracle,
         "smoother": sm,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -119,39 +119,6 @@ __device__ __forceinline__ double eno_2h(double fm2, double fm1, double f0, doub
   return fp1 - fm1;
 }
 
-// (u . grad) f at cell t for one cell field f (Eq. sig_star_evol's advection
-// with Eq. ENO per axis): x and y wrap; in z, layers past the walls continue
-// the two nearest layers linearly.
-__device__ __forceinline__ double eno_advection(const double* __restrict__ f, int nx, int ny, int nz,
-                                                const CellIdx& c, int t, const double u[3],
-                                                double h) {
-#pragma clang fp contract(off)
-  const int P = nx * ny;
-  double g[5];
-  // x
-#pragma unroll
-  for (int o = -2; o <= 2; ++o) g[o + 2] = f[t - c.i + (c.i + o + 2 * nx) % nx];
-  const double dx = eno_2h(g[0], g[1], g[2], g[3], g[4], u[0]);
-  // y
-#pragma unroll
-  for (int o = -2; o <= 2; ++o) g[o + 2] = f[t + ((c.j + o + 2 * ny) % ny - c.j) * nx];
-  const double dy = eno_2h(g[0], g[1], g[2], g[3], g[4], u[1]);
-  // z, with the ghost layers
-  const int col = t - c.k * P;
-  const double b0 = f[col], b1 = f[col + P];
-  const double t1 = f[col + (nz - 1) * P], t0 = f[col + (nz - 2) * P];
-  const double d0 = b1 - b0, d1 = t1 - t0;
-#pragma unroll
-  for (int o = -2; o <= 2; ++o) {
-    const int e = c.k + o;
-    g[o + 2] = e < 0 ? (e == -1 ? b0 - d0 : b0 - 2.0 * d0)
-                     : (e > nz - 1 ? (e == nz ? t1 + d1 : t1 + 2.0 * d1) : f[col + e * P]);
-  }
-  const double dz = eno_2h(g[0], g[1], g[2], g[3], g[4], u[2]);
-  const double h2 = 2.0 * h;
-  return u[0] * (dx / h2) + u[1] * (dy / h2) + u[2] * (dz / h2);
-}
-
 // D^pl alone (Eq. stz_dpl), for the sub-step loop.
 __device__ __forceinline__ double plastic_D(double sbar, double chi, const StzArgs& a) {
   if (!(sbar > a.s_y)) return 0.0;
@@ -259,27 +226,23 @@ __global__ __launch_bounds__(256) void k_dpl_cells(const double* __restrict__ si
   D[t] = dpl_cell(sigma, chi, N, t, a);
 }
 
-template <bool DIFF, bool ADV>
-__global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
-                                                  const double* __restrict__ sigma,
-                                                  const double* __restrict__ chi,
-                                                  double* __restrict__ sstar,
-                                                  double* __restrict__ chi1,
-                                                  const double* __restrict__ Dcell, int nx, int ny,
-                                                  int nz, StzArgs a) {
-  CellIdx c;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (!cell_of(t, nx, ny, nz, &c)) return;
+// The cell update of the STZ step from the velocity gradient L, the stress S
+// and chi of cell t (and, with ADV, adv(n) = the advection term
+// (u . grad) sigma of Voigt component n, evaluated when that component is
+// written): writes sigma*[.][t] and chi'[t].
+template <bool DIFF, bool ADV, typename Adv>
+__device__ __forceinline__ void stz_update(const double* __restrict__ sigma,
+                                           const double* __restrict__ chi,
+                                           double* __restrict__ sstar, double* __restrict__ chi1,
+                                           const double* __restrict__ Dcell, int nx, int ny, int nz,
+                                           const CellIdx& c, int t, const double L[3][3],
+                                           const double S[3][3], double x, const Adv& adv,
+                                           const StzArgs& a) {
   const int N = nx * ny * nz;
-  double L[3][3], S[3][3], S0[3][3], sbar;
-  cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
-  load_voigt(sigma, N, t, S);
+  double S0[3][3], sbar;
   deviator(S, S0, &sbar);
-  const double x = chi[t];
   const Plastic pl = plastic_rate(sbar, x, a);
   const double trL = L[0][0] + L[1][1] + L[2][2];
-  double u[3] = {0.0, 0.0, 0.0};
-  if (ADV) cell_velocity(v, nx, ny, nz, c, u);
   double xn;
   if (a.n_sub == 1) {
     const double rho = pl.D > 0.0 ? pl.D / sbar : 0.0;
@@ -295,7 +258,7 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
       }
       const double rate = LS + SLt - trL * S[p][q] - 2.0 * a.mu * rho * S0[p][q];
       double val = S[p][q] + a.dt * rate;
-      if (ADV) val = val - a.dt * eno_advection(sigma + n * N, nx, ny, nz, c, t, u, a.h);
+      if (ADV) val = val - a.dt * adv(n);
       sstar[n * N + t] = val;
     }
     xn = x + (a.dt / a.c0) * (2.0 * sbar * pl.D / a.s_y) * (a.chi_inf - x);
@@ -330,7 +293,7 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
         SLt += S[p][m] * L[q][m];
       }
       double val = (S[p][q] - (1.0 - scale) * S0[p][q]) + a.dt * (LS + SLt - trL * S[p][q]);
-      if (ADV) val = val - a.dt * eno_advection(sigma + n * N, nx, ny, nz, c, t, u, a.h);
+      if (ADV) val = val - a.dt * adv(n);
       sstar[n * N + t] = val;
     }
   } else {
@@ -367,7 +330,7 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
         SLt += S[p][m] * L[q][m];
       }
       double val = Sp[p][q] + a.dt * (LS + SLt - trL * S[p][q]);
-      if (ADV) val = val - a.dt * eno_advection(sigma + n * N, nx, ny, nz, c, t, u, a.h);
+      if (ADV) val = val - a.dt * adv(n);
       sstar[n * N + t] = val;
     }
     xn = xp;
@@ -378,6 +341,112 @@ __global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
     xn = xn + (a.dt / a.c0) * a.l2 * chi_flux_divergence(sigma, chi, Dcell, nx, ny, nz, c, t, Dc, x, a);
   }
   chi1[t] = xn;
+}
+
+// One thread per cell (no advection).
+template <bool DIFF>
+__global__ __launch_bounds__(256) void k_stz_step(const double* __restrict__ v,
+                                                  const double* __restrict__ sigma,
+                                                  const double* __restrict__ chi,
+                                                  double* __restrict__ sstar,
+                                                  double* __restrict__ chi1,
+                                                  const double* __restrict__ Dcell, int nx, int ny,
+                                                  int nz, StzArgs a) {
+  CellIdx c;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (!cell_of(t, nx, ny, nz, &c)) return;
+  double L[3][3], S[3][3];
+  cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
+  load_voigt(sigma, nx * ny * nz, t, S);
+  stz_update<DIFF, false>(sigma, chi, sstar, chi1, Dcell, nx, ny, nz, c, t, L, S, chi[t],
+                          [](int) { return 0.0; }, a);
+}
+
+// sigma of one Voigt component f at plane e of column col; in z, the layers
+// past the walls continue the two nearest layers linearly (Sec. 3.5).
+__device__ __forceinline__ double z_layer(const double* __restrict__ f, int P, int nz, int col,
+                                          int e) {
+#pragma clang fp contract(off)
+  if (e >= 0 && e <= nz - 1) return f[col + e * P];
+  if (e < 0) {
+    const double b0 = f[col], b1 = f[col + P];
+    const double d0 = b1 - b0;
+    return e == -1 ? b0 - d0 : b0 - 2.0 * d0;
+  }
+  const double t1 = f[col + (nz - 1) * P], t0 = f[col + (nz - 2) * P];
+  const double d1 = t1 - t0;
+  return e == nz ? t1 + d1 : t1 + 2.0 * d1;
+}
+
+// With the advection of the stress (Eq. sig_star_evol): one thread per cell,
+// a workgroup per 16 x 16 tile of one cell plane.  Eq. ENO reads two cells on
+// each side along x, y and z, so the mapping keeps those reads in cache: a
+// band of 16 rows (all tiles along x, so the x wrap stays inside it) goes to
+// one XCD (workgroup w runs on XCD w mod 8), whose workgroups take the band
+// plane after plane and tile after tile.  The planes k-2 .. k+2 of a band are
+// then in flight together and share that XCD's L2, and only the two rows on
+// each side of the band come from elsewhere.  Each derivative is Eq. ENO along its axis (x and y
+// wrap; in z the layers past the walls continue the two nearest layers
+// linearly, Sec. 3.5), with u the mean of the cell's eight corner velocities;
+// no fused multiply-adds here, so the branch choices of Eq. ENO are taken on
+// the same FP64 values as the oracle's.
+constexpr int kTile = 16;
+
+template <bool DIFF>
+__global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __restrict__ v,
+                                                               const double* __restrict__ sigma,
+                                                               const double* __restrict__ chi,
+                                                               double* __restrict__ sstar,
+                                                               double* __restrict__ chi1,
+                                                               const double* __restrict__ Dcell,
+                                                               int nx, int ny, int nz, int ntx,
+                                                               int bands, StzArgs a) {
+#pragma clang fp contract(off)
+  const int w = blockIdx.x;
+  const int xcd = w & 7, slot = w >> 3;
+  const int per_band = nz * ntx;
+  const int band = (slot / per_band) * 8 + xcd;
+  if (band >= bands) return;
+  const int r = slot - (slot / per_band) * per_band;
+  const int k = r / ntx, tx = r - k * ntx;
+  CellIdx c;
+  c.i = tx * kTile + static_cast<int>(threadIdx.x) % kTile;
+  c.j = band * kTile + static_cast<int>(threadIdx.x) / kTile;
+  if (c.i >= nx || c.j >= ny) return;
+  c.k = k;
+  c.ip = c.i + 1 == nx ? 0 : c.i + 1;
+  c.jp = c.j + 1 == ny ? 0 : c.j + 1;
+  const int P = nx * ny, N = P * nz;
+  const int col = c.j * nx + c.i;
+  const int t = k * P + col;
+  const int im1 = c.i == 0 ? nx - 1 : c.i - 1, im2 = im1 == 0 ? nx - 1 : im1 - 1;
+  const int ip2 = c.ip + 1 == nx ? 0 : c.ip + 1;
+  const int jm1 = c.j == 0 ? ny - 1 : c.j - 1, jm2 = jm1 == 0 ? ny - 1 : jm1 - 1;
+  const int jp2 = c.jp + 1 == ny ? 0 : c.jp + 1;
+  const int xo[4] = {im2 - c.i, im1 - c.i, c.ip - c.i, ip2 - c.i};
+  const int yo[4] = {(jm2 - c.j) * nx, (jm1 - c.j) * nx, (c.jp - c.j) * nx, (jp2 - c.j) * nx};
+  double L[3][3], S[3][3], u[3];
+  cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
+  cell_velocity(v, nx, ny, nz, c, u);
+  // the six advection terms, one component at a time (a loop that is not
+  // unrolled keeps one copy of the stencil code and few registers), parked in
+  // LDS slots of this thread until the update writes each component
+  __shared__ double advs[6][kTile * kTile];
+  const double ih2 = 1.0 / (2.0 * a.h);
+#pragma unroll 1
+  for (int n = 0; n < 6; ++n) {
+    const double* f = sigma + n * N + t;
+    const double f0 = f[0];
+    const double dx = eno_2h(f[xo[0]], f[xo[1]], f0, f[xo[2]], f[xo[3]], u[0]);
+    const double dy = eno_2h(f[yo[0]], f[yo[1]], f0, f[yo[2]], f[yo[3]], u[1]);
+    const double* g = sigma + n * N;
+    const double dz = eno_2h(z_layer(g, P, nz, col, k - 2), z_layer(g, P, nz, col, k - 1), f0,
+                             z_layer(g, P, nz, col, k + 1), z_layer(g, P, nz, col, k + 2), u[2]);
+    advs[n][threadIdx.x] = (u[0] * dx + u[1] * dy + u[2] * dz) * ih2;
+  }
+  load_voigt(sigma, N, t, S);
+  stz_update<DIFF, true>(sigma, chi, sstar, chi1, Dcell, nx, ny, nz, c, t, L, S, chi[t],
+                         [&](int n) { return advs[n][threadIdx.x]; }, a);
 }
 
 // Node divergence of a cell field (corner form of Eq. stag_stenc): for
@@ -806,18 +875,26 @@ void launch_stz_step(const double* v, const double* sigma, const double* chi, do
   // the diffusion term reads D^pl of the six face neighbours: one pass first
   if (a.l2 > 0.0)
     hipLaunchKernelGGL(k_dpl_cells, grid, block, 0, s, sigma, chi, dcell, static_cast<int>(n), a);
-  if (a.l2 > 0.0 && a.advect)
-    hipLaunchKernelGGL((k_stz_step<true, true>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       dcell, d.nx, d.ny, d.nz, a);
-  else if (a.l2 > 0.0)
-    hipLaunchKernelGGL((k_stz_step<true, false>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       dcell, d.nx, d.ny, d.nz, a);
-  else if (a.advect)
-    hipLaunchKernelGGL((k_stz_step<false, true>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       dcell, d.nx, d.ny, d.nz, a);
-  else
-    hipLaunchKernelGGL((k_stz_step<false, false>), grid, block, 0, s, v, sigma, chi, sstar, chi1,
-                       dcell, d.nx, d.ny, d.nz, a);
+  if (a.advect) {
+    // z-segments of 32 cell planes, fewer when that leaves too few workgroups
+    // one workgroup per (16 x 16 tile, plane); bands of 16 rows dealt
+    // round-robin to the eight XCDs, each band plane by plane on its XCD
+    const int ntx = (d.nx + kTile - 1) / kTile, bands = (d.ny + kTile - 1) / kTile;
+    const long long wgs = 8LL * ((bands + 7) / 8) * d.nz * ntx;
+    const dim3 g2(static_cast<unsigned>(wgs)), b2(kTile * kTile);
+    if (a.l2 > 0.0)
+      hipLaunchKernelGGL((k_stz_step_adv<true>), g2, b2, 0, s, v, sigma, chi, sstar, chi1, dcell,
+                         d.nx, d.ny, d.nz, ntx, bands, a);
+    else
+      hipLaunchKernelGGL((k_stz_step_adv<false>), g2, b2, 0, s, v, sigma, chi, sstar, chi1, dcell,
+                         d.nx, d.ny, d.nz, ntx, bands, a);
+  } else if (a.l2 > 0.0) {
+    hipLaunchKernelGGL((k_stz_step<true>), grid, block, 0, s, v, sigma, chi, sstar, chi1, dcell,
+                       d.nx, d.ny, d.nz, a);
+  } else {
+    hipLaunchKernelGGL((k_stz_step<false>), grid, block, 0, s, v, sigma, chi, sstar, chi1, dcell,
+                       d.nx, d.ny, d.nz, a);
+  }
 }
 
 void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hipStream_t s) {

@@ -66,6 +66,32 @@ def test_config2_residual_at_256(prec):
     assert np.isfinite(rel)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
+def test_config2_error_against_oracle_solution_256(prec):
+    """256^3 solve to 1e-10 against the oracle's own solution of the same
+    system (solved to 1e-12 by tests/golden/make_solve256.py, which calls only
+    the oracle) at 4096 stored interior nodes: relative L2 difference <= 1e-8
+    (observed about 1e-10), and the solution norm to the same bound."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "solve256.json")))
+    n = ref["n"]
+    g = solver(n, precision=prec)
+    sig = dev(stress_field(n, n, n, 2))
+    b = g.rhs(sig, 1.0)
+    del sig
+    x = torch.zeros_like(b)
+    info = g.solve(b, x, rtol=1e-10)
+    assert info.converged
+    idx = torch.tensor(ref["sample_index"], device="cuda")
+    got = x[:, idx[:, 0], idx[:, 1], idx[:, 2]].T
+    want = torch.tensor(ref["sample_x"], dtype=torch.float64, device="cuda")
+    err = (torch.linalg.vector_norm(got - want) / torch.linalg.vector_norm(want)).item()
+    nerr = abs(torch.linalg.vector_norm(x).item() - ref["x_norm"]) / ref["x_norm"]
+    print("%s: sampled error %.3e, norm error %.3e" % (prec, err, nerr))
+    assert err <= 1e-8 and nerr <= 1e-8, (err, nerr)
+
+
 def test_config2_at_512():
     """512^3 (7 levels), FP64 and FP32-IR to 1e-10 on b = D_h sigma of the
     smoothed random stress (device generator, seed 2).  The oracle's operator,
