@@ -292,9 +292,12 @@ bool use_row_sweep(qs_handle* hd, int l) {
 // x_zero: the interior of x is known to be zero (its walls are zero too), so
 // the first forward sweep does not read it; the sweep writes every interior
 // node of the other buffer, so x need not even hold zeros then.
+// prolong: the coarse correction of level l + 1 (reverse sweeps on a level
+// with the row sweep only): the first sweep adds x += T prolong on the fly
+// instead of a separate prolongation.
 template <typename T>
 void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse,
-            bool x_zero = false) {
+            bool x_zero = false, const T* prolong = nullptr) {
   if (sweeps <= 0) return;
   LevelBufs& lb = hd->L[l];
   const int* ord = hd->p.colour_order;
@@ -323,10 +326,12 @@ void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse,
   const int rp0 = reverse ? 1 : 0, pf = reverse ? 1 : 0, xf = reverse ? 1 : 0;
   for (int s = 0; s < sweeps; ++s) {
     const bool z = x_zero && s == 0 && !reverse;
-    launch_sweep_half<T>(cur, cur, oth, b, lb.d, rp0, pf, xf, cf, Prec<T>::seg(lb), 1, z ? 2 : 0,
-                         hd->stream);
-    launch_sweep_half<T>(cur, oth, oth, b, lb.d, 1 - rp0, pf, xf, cf, Prec<T>::seg(lb), 1,
-                         z ? 1 : 0, hd->stream);
+    const bool pro = prolong && s == 0 && reverse;
+    const T* ec = pro ? prolong : nullptr;
+    launch_sweep_half<T>(cur, cur, oth, b, ec, lb.d, rp0, pf, xf, cf, Prec<T>::seg(lb), 1,
+                         z ? 2 : (pro ? 3 : 0), hd->stream);
+    launch_sweep_half<T>(cur, oth, oth, b, ec, lb.d, 1 - rp0, pf, xf, cf, Prec<T>::seg(lb), 1,
+                         z ? 1 : (pro ? 4 : 0), hd->stream);
     T* t = cur;
     cur = oth;
     oth = t;
@@ -356,6 +361,11 @@ void vcycle(qs_handle* hd, int l, T* x, const T* b, bool x_zero = false) {
     launch_restrict<T>(r, Prec<T>::b(cb), Prec<T>::x(cb), lb.d, hd->stream);
   }
   vcycle<T>(hd, l + 1, Prec<T>::x(cb), Prec<T>::b(cb));
+  if (hd->p.n_post >= 1 && use_row_sweep<T>(hd, l)) {
+    // the first post-smoothing sweep applies the prolongated correction
+    smooth<T>(hd, l, x, b, hd->p.n_post, true, false, Prec<T>::x(cb));
+    return;
+  }
   launch_prolong_add<T>(x, Prec<T>::x(cb), lb.d, hd->stream);
   smooth<T>(hd, l, x, b, hd->p.n_post, true);
 }

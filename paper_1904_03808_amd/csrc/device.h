@@ -71,10 +71,14 @@ void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* S, 
 // of the rows with parity row_par, reading own rows from own_src, neighbour
 // rows from nbr_src and writing dst.  zero = 1: own rows are known to be 0
 // and not read; zero = 2: own and neighbour rows (x_first = 0 only).
+// zero = 3: own and neighbour rows are read as x + T ec (the coarse
+// correction ec prolongated on the fly); zero = 4: own rows only (both
+// x_first = 1, row_par 1 and 0, the two halves of the first post-smoothing
+// sweep; ec is the coarse level's correction, null otherwise).
 template <typename T>
-void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
-                       int plane_first, int x_first, const FineCoef<T>& cf, int seg, int seg_major,
-                       int zero, hipStream_t s);
+void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, const T* ec, Dims d,
+                       int row_par, int plane_first, int x_first, const FineCoef<T>& cf, int seg,
+                       int seg_major, int zero, hipStream_t s);
 int sweep_rows_per_group(int nx);  // rows of one parity per workgroup
 int sweep_segment_length(Dims d, int bytes_per_value);  // z planes per workgroup
 int sweep_lds_bytes(Dims d, int bytes_per_value);

@@ -92,6 +92,12 @@ struct Ctx {
   int j, jm, jp;
   size_t P, C;
   bool write;  // false for rows past the last one of this parity (last group)
+  // prolongation variants (Z = 3, 4): the coarse correction ec, its plane
+  // and component strides, the coarse columns I, I+1 of this pair and the
+  // coarse rows A (row j-1, or j for even j) and B (row j+1)
+  const T* ec;
+  size_t Pc, Cc;
+  int nzc, I, I1, JA, JB;
   __device__ __forceinline__ int nxp() const { return (NX > 0 ? NX : nx) + 2 * kPad; }
   // column 0 of LDS row q = 3 rr + component of this thread's rows
   // (rr 0, 1, 2 = j-1, j, j+1) in the plane held in ring slot (plane & 3);
@@ -112,7 +118,12 @@ struct PlaneRegs {
 
 // Z = 0: rows as stored; Z = 1: the thread's own row reads as zero; Z = 2:
 // own and neighbour rows read as zero (a vector known to be zero is not
-// fetched).
+// fetched); Z = 3: own and neighbour rows read as x + T e_c, the coarse-grid
+// correction prolongated on the fly (the first half of the first
+// post-smoothing sweep, which thereby also applies the correction); Z = 4:
+// the own rows read as x + T e_c (its second half: the neighbour rows come
+// corrected from the first half's output).  The correction is added where the
+// registers go into the ring (correct_plane).
 template <typename T, int NX, int Z>
 __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __restrict__ own_src,
                                             const T* __restrict__ nbr_src, int p,
@@ -127,13 +138,91 @@ __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __rest
   const V zero = V{T(0), T(0)};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    out.v[k] = Z >= 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + om);
-    out.v[3 + k] = Z >= 1 ? zero : NT2<T>::template load<V>(own_src + k * c.C + oo);
+    out.v[k] = Z == 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + om);
+    out.v[3 + k] = (Z == 1 || Z == 2) ? zero : NT2<T>::template load<V>(own_src + k * c.C + oo);
   }
   if (top) {
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      out.v[6 + k] = Z >= 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + op);
+      out.v[6 + k] = Z == 2 ? zero : *reinterpret_cast<const V*>(nbr_src + k * c.C + op);
+  }
+}
+
+// Coarse values behind the correction of two consecutive fine planes: coarse
+// planes Ka and Ka + 1 (clamped to the top wall, whose values are zero), rows
+// A and B (Z = 3) or A (Z = 4), columns I and I + 1, three components.
+template <typename T>
+struct CoarseRegs {
+  T e[2][2][2][3];  // [plane Ka, Ka+1][row A, B][column I, I+1][component]
+};
+
+template <typename T, int NX, int Z>
+__device__ __forceinline__ void fetch_coarse(const Ctx<T, NX>& c, int Ka, CoarseRegs<T>& out) {
+  if (Z != 3 && Z != 4) return;
+#pragma unroll
+  for (int kp = 0; kp < 2; ++kp) {
+    const size_t base = static_cast<size_t>(min(Ka + kp, c.nzc)) * c.Pc;
+    const int nxc = NX > 0 ? NX / 2 : c.nx / 2;
+#pragma unroll
+    for (int rb = 0; rb < (Z == 3 ? 2 : 1); ++rb) {
+      const size_t o = base + static_cast<size_t>(rb ? c.JB : c.JA) * nxc;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        out.e[kp][rb][0][k] = c.ec[k * c.Cc + o + c.I];
+        out.e[kp][rb][1][k] = c.ec[k * c.Cc + o + c.I1];
+      }
+    }
+  }
+}
+
+// x + T e_c for the fine plane p (coarse planes Ka, Ka+1 in ce) on the rows
+// of `in` that need it, in the arithmetic of k_prolong_add: the x, y
+// combination of each coarse plane, then the z mean on odd planes.
+template <typename T, int NX, int Z>
+__device__ __forceinline__ void correct_plane(const Ctx<T, NX>& c, int p, int Ka,
+                                              const CoarseRegs<T>& ce, PlaneRegs<T>& in) {
+  if (Z != 3 && Z != 4) return;
+  const T h = T(0.5);
+  const int k0 = (p >> 1) - Ka, k1 = min((p + 1) >> 1, c.nzc) - Ka;
+  const bool oz = p & 1;
+  // fine rows: q = 0 row j-1, 1 row j, 2 row j+1 (top thread only)
+  const bool top = c.r == c.rows - 1;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (Z == 4 && q != 1) continue;      // own row only
+    if (q == 2 && !top) continue;
+    // Z = 3: j is odd, rows j-1 and j+1 even (coarse rows A and B), row j
+    // between them; Z = 4: j is even, coarse row A
+    const bool oy = Z == 3 && q == 1;
+    const int ra = (Z == 3 && q == 2) ? 1 : 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      // x, y combination of both coarse planes (static indices, so that the
+      // coarse values stay in registers), then the planes this fine plane uses
+      T pe[2], po[2];
+#pragma unroll
+      for (int kp = 0; kp < 2; ++kp) {
+        const T a0 = ce.e[kp][ra][0][k], a1 = ce.e[kp][ra][1][k];
+        if (oy) {
+          const T b0 = ce.e[kp][1][0][k], b1 = ce.e[kp][1][1][k];
+          pe[kp] = h * (a0 + b0);
+          po[kp] = h * (h * (a0 + a1) + h * (b0 + b1));
+        } else {
+          pe[kp] = a0;
+          po[kp] = h * (a0 + a1);
+        }
+      }
+      const T pe0 = k0 ? pe[1] : pe[0], po0 = k0 ? po[1] : po[0];
+      const T pe1 = k1 ? pe[1] : pe[0], po1 = k1 ? po[1] : po[0];
+      typename V2<T>::type& v = in.v[3 * q + k];
+      if (oz) {
+        v.x += h * (pe0 + pe1);
+        v.y += h * (po0 + po1);
+      } else {
+        v.x += pe0;
+        v.y += po0;
+      }
+    }
   }
 }
 
@@ -252,21 +341,23 @@ __device__ __forceinline__ void update_plane(const Ctx<T, NX>& c, int p, int z0,
 
 // Registers of one step of the march at first-parity plane f: planes f+2
 // and f+3 and b at planes f+2 and f+1.
-template <typename T>
+template <typename T, int Z>
 struct StepRegs {
   PlaneRegs<T> p2, p3;
   typename V2<T>::type bf[3], bs[3];
+  CoarseRegs<T> ce[1];  // Z = 3, 4 only
 };
 
 // Issue the loads of the step whose planes are g = f+2 and g+1.
 template <typename T, int NX, int Z>
 __device__ __forceinline__ void fetch_step(const Ctx<T, NX>& c, const T* __restrict__ own_src,
                                            const T* __restrict__ nbr_src, const T* __restrict__ b,
-                                           int g, int nz, StepRegs<T>& s) {
+                                           int g, int nz, StepRegs<T, Z>& s) {
   fetch_b<T, NX>(c, b, g, nz, s.bf);
   fetch_b<T, NX>(c, b, g - 1, nz, s.bs);
   fetch_plane<T, NX, Z>(c, own_src, nbr_src, min(g, nz), s.p2);
   fetch_plane<T, NX, Z>(c, own_src, nbr_src, min(g + 1, nz), s.p3);
+  fetch_coarse<T, NX, Z>(c, min(g, nz) >> 1, s.ce[0]);
 }
 
 // One step of the march: issue the loads for two steps ahead into `nxt`,
@@ -277,8 +368,8 @@ __device__ __forceinline__ void march_step(const Ctx<T, NX>& c, const T* __restr
                                            const T* __restrict__ nbr_src, const T* __restrict__ b,
                                            T* __restrict__ dst, const FineCoef<T>& cf, int f,
                                            int z0, int z1, int nz, typename V2<T>::type bf[3],
-                                           typename V2<T>::type bs[3], StepRegs<T>& cur,
-                                           StepRegs<T>& nxt) {
+                                           typename V2<T>::type bs[3], StepRegs<T, Z>& cur,
+                                           StepRegs<T, Z>& nxt) {
   fetch_step<T, NX, Z>(c, own_src, nbr_src, b, f + 4, nz, nxt);
   update_plane<T, NX, X1>(c, f, z0, z1, bf, cf, dst);
   __syncthreads();
@@ -286,6 +377,11 @@ __device__ __forceinline__ void march_step(const Ctx<T, NX>& c, const T* __restr
   if (sp >= z0 && sp <= z1 - 1 && sp >= 1) {
     update_plane<T, NX, X1>(c, sp, z0, z1, bs, cf, dst);
     __syncthreads();
+  }
+  {
+    const int Ka = min(f + 2, nz) >> 1;  // as fetch_step
+    correct_plane<T, NX, Z>(c, min(f + 2, nz), Ka, cur.ce[0], cur.p2);
+    correct_plane<T, NX, Z>(c, min(f + 3, nz), Ka, cur.ce[0], cur.p3);
   }
   if (f + 2 <= nz) store_plane<T, NX>(c, f + 2, cur.p2);
   if (f + 3 <= nz) store_plane<T, NX>(c, f + 3, cur.p3);
@@ -304,6 +400,7 @@ template <typename T, int NX, int X1, int Z>
 __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* __restrict__ own_src,
                                                     const T* __restrict__ nbr_src,
                                                     T* __restrict__ dst, const T* __restrict__ b,
+                                                    const T* __restrict__ ec,
                                                     SweepArgs a, FineCoef<T> cf) {
   using V = typename V2<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -337,6 +434,17 @@ __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* _
   c.jp = c.j + 1 >= a.ny ? c.j + 1 - a.ny : c.j + 1;
   c.P = static_cast<size_t>(c.nx) * a.ny;
   c.C = static_cast<size_t>(a.nz + 1) * c.P;
+  if (Z == 3 || Z == 4) {
+    const int nxc = c.nx / 2, nyc = a.ny / 2;
+    c.ec = ec;
+    c.nzc = a.nz / 2;
+    c.Pc = static_cast<size_t>(nxc) * nyc;
+    c.Cc = static_cast<size_t>(c.nzc + 1) * c.Pc;
+    c.I = c.c0 >> 1;
+    c.I1 = c.I + 1 == nxc ? 0 : c.I + 1;
+    c.JA = Z == 3 ? (c.jm >> 1) : (c.j >> 1);
+    c.JB = c.jp >> 1;
+  }
 
   const int nz = a.nz;
   const int z0 = 1 + sgi * a.seg;
@@ -362,13 +470,25 @@ __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* _
   V bf[3], bs[3];
   fetch_b<T, NX>(c, b, f0, nz, bf);
   fetch_b<T, NX>(c, b, f0 - 1, nz, bs);
-  StepRegs<T> ra, rb;
+  StepRegs<T, Z> ra, rb;
   {
     PlaneRegs<T> q0, q1, q2, q3;
     fetch_plane<T, NX, Z>(c, own_src, nbr_src, max(f0 - 2, 0), q0);
     fetch_plane<T, NX, Z>(c, own_src, nbr_src, f0 - 1, q1);
     fetch_plane<T, NX, Z>(c, own_src, nbr_src, f0, q2);
     fetch_plane<T, NX, Z>(c, own_src, nbr_src, f0 + 1, q3);  // f0 + 1 <= nz
+    if (Z == 3 || Z == 4) {
+      // coarse planes of the fine planes f0-2 .. f0+1 (first loads of the march)
+      CoarseRegs<T> lo, hi;
+      const int Klo = max(f0 - 2, 0) >> 1, Khi = f0 >> 1;
+      fetch_coarse<T, NX, Z>(c, Klo, lo);
+      fetch_coarse<T, NX, Z>(c, Khi, hi);
+      correct_plane<T, NX, Z>(c, max(f0 - 2, 0), Klo, lo, q0);
+      // plane f0 - 1 needs coarse planes (f0-1)>>1 and f0>>1: within [Klo, Klo + 1]
+      correct_plane<T, NX, Z>(c, f0 - 1, Klo, lo, q1);
+      correct_plane<T, NX, Z>(c, f0, Khi, hi, q2);
+      correct_plane<T, NX, Z>(c, f0 + 1, Khi, hi, q3);
+    }
     fetch_step<T, NX, Z>(c, own_src, nbr_src, b, f0 + 2, nz, ra);
     if (first == f0 - 2) store_plane<T, NX>(c, f0 - 2, q0);
     store_plane<T, NX>(c, f0 - 1, q1);
@@ -387,29 +507,36 @@ __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* _
 }
 
 template <typename T, int NX>
-void launch_nx(const T* own_src, const T* nbr_src, T* dst, const T* b, const SweepArgs& a,
-               const FineCoef<T>& cf, int zero, int threads, size_t lds, hipStream_t s) {
+void launch_nx(const T* own_src, const T* nbr_src, T* dst, const T* b, const T* ec,
+               const SweepArgs& a, const FineCoef<T>& cf, int zero, int threads, size_t lds,
+               hipStream_t s) {
   const dim3 grid(8 * a.grid_per_xcd), block(threads);
-  if (a.x_first)
-    hipLaunchKernelGGL((k_sweep_rows<T, NX, 1, 0>), grid, block, lds, s, own_src, nbr_src, dst, b,
-                       a, cf);
+#define QS_SWEEP(X1, Z)                                                                        \
+  hipLaunchKernelGGL((k_sweep_rows<T, NX, X1, Z>), grid, block, lds, s, own_src, nbr_src, dst, b, \
+                     ec, a, cf)
+  if (a.x_first && zero == 3)
+    QS_SWEEP(1, 3);
+  else if (a.x_first && zero == 4)
+    QS_SWEEP(1, 4);
+  else if (a.x_first)
+    QS_SWEEP(1, 0);
   else if (zero == 2)
-    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0, 2>), grid, block, lds, s, own_src, nbr_src, dst, b,
-                       a, cf);
+    QS_SWEEP(0, 2);
   else if (zero == 1)
-    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0, 1>), grid, block, lds, s, own_src, nbr_src, dst, b,
-                       a, cf);
+    QS_SWEEP(0, 1);
   else
-    hipLaunchKernelGGL((k_sweep_rows<T, NX, 0, 0>), grid, block, lds, s, own_src, nbr_src, dst, b,
-                       a, cf);
+    QS_SWEEP(0, 0);
+#undef QS_SWEEP
 }
 
 template <typename T, int NX>
 void set_lds_limit_one(int bytes) {
-  const void* k[4] = {reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 0>),
+  const void* k[6] = {reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 0>),
                       reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 1, 0>),
                       reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 1>),
-                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 2>)};
+                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 0, 2>),
+                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 1, 3>),
+                      reinterpret_cast<const void*>(&k_sweep_rows<T, NX, 1, 4>)};
   for (const void* f : k)
     (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
@@ -483,8 +610,8 @@ bool sweep_supported(Dims d, size_t lds_limit, int bytes_per_value) {
 }
 
 template <typename T>
-void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, Dims d, int row_par,
-                       int plane_first, int x_first, const FineCoef<T>& cf, int seg,
+void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, const T* ec, Dims d,
+                       int row_par, int plane_first, int x_first, const FineCoef<T>& cf, int seg,
                        int seg_major, int zero, hipStream_t s) {
   SweepArgs a;
   a.nx = d.nx;
@@ -504,12 +631,12 @@ void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, D
   const int threads = a.rows * (d.nx / 2);
   const size_t lds = static_cast<size_t>(sweep_lds_bytes(d, sizeof(T)));
   switch (d.nx) {
-    case 128: launch_nx<T, 128>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
-    case 256: launch_nx<T, 256>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
-    case 384: launch_nx<T, 384>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
-    case 512: launch_nx<T, 512>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
-    case 768: launch_nx<T, 768>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
-    default: launch_nx<T, 0>(own_src, nbr_src, dst, b, a, cf, zero, threads, lds, s); break;
+    case 128: launch_nx<T, 128>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
+    case 256: launch_nx<T, 256>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
+    case 384: launch_nx<T, 384>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
+    case 512: launch_nx<T, 512>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
+    case 768: launch_nx<T, 768>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
+    default: launch_nx<T, 0>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
   }
 }
 
@@ -518,11 +645,11 @@ void sweep_set_lds_limit(size_t bytes) {
   set_lds_limit_all<float>(static_cast<int>(bytes));
 }
 
-template void launch_sweep_half<double>(const double*, const double*, double*, const double*, Dims,
-                                        int, int, int, const FineCoef<double>&, int, int, int,
-                                        hipStream_t);
-template void launch_sweep_half<float>(const float*, const float*, float*, const float*, Dims, int,
-                                       int, int, const FineCoef<float>&, int, int, int,
-                                       hipStream_t);
+template void launch_sweep_half<double>(const double*, const double*, double*, const double*,
+                                        const double*, Dims, int, int, int,
+                                        const FineCoef<double>&, int, int, int, hipStream_t);
+template void launch_sweep_half<float>(const float*, const float*, float*, const float*,
+                                       const float*, Dims, int, int, int, const FineCoef<float>&,
+                                       int, int, int, hipStream_t);
 
 }  // namespace qs
