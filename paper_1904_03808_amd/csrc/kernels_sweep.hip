@@ -72,9 +72,20 @@ struct SweepArgs {
   int real_wgs;      // ngroups * nseg
   int grid_per_xcd;  // padded grid / 8
   int seg_major;     // 1: consecutive workgroups take consecutive row groups of one segment
+  int xs;            // column segments per row (2 for FP64 rows of 768, else 1)
 };
 
 constexpr int kPad = 2;  // LDS row: [unused][copy of col nx-1][cols 0..nx-1][copy of col 0][unused]
+// FP64 rows of 768 nodes do not fit the ring of one workgroup (223 KB of LDS):
+// there two workgroups share a row, each holding its 384 columns and kHalo
+// columns on either side, which it updates as well (from the same old values,
+// so that its own columns see exact neighbours) but does not write.  Wrong
+// values at a halo's outer edge travel inward one column per update phase,
+// three columns within a step (the two x-parity phases of a first-parity
+// plane, then of the second-parity plane below it); the next step starts
+// again from old values, so four halo columns keep every written column exact.
+constexpr int kHalo = 4;
+constexpr int kSplitW = 384;
 
 // rows of one parity per workgroup: two at 256 columns, more for shorter rows
 // (at most 256 threads), one at 384, 512 and 768 (384 threads)
@@ -92,13 +103,19 @@ struct Ctx {
   int j, jm, jp;
   size_t P, C;
   bool write;  // false for rows past the last one of this parity (last group)
+  // rows of 768 FP64 values: split into two column segments (see kHalo)
+  static constexpr bool kSplit = NX == 768 && sizeof(T) == 8;
+  int gc0;       // global column of this thread's pair (c0 without the split)
+  bool own_col;  // the pair is one the workgroup writes (not halo)
   // prolongation variants (Z = 3, 4): the coarse correction ec, its plane
   // and component strides, the coarse columns I, I+1 of this pair and the
   // coarse rows A (row j-1, or j for even j) and B (row j+1)
   const T* ec;
   size_t Pc, Cc;
   int nzc, I, I1, JA, JB;
-  __device__ __forceinline__ int nxp() const { return (NX > 0 ? NX : nx) + 2 * kPad; }
+  __device__ __forceinline__ int nxp() const {
+    return (kSplit ? kSplitW + 2 * kHalo : (NX > 0 ? NX : nx)) + 2 * kPad;
+  }
   // column 0 of LDS row q = 3 rr + component of this thread's rows
   // (rr 0, 1, 2 = j-1, j, j+1) in the plane held in ring slot (plane & 3);
   // the rows of a workgroup are consecutive, so the neighbour row between two
@@ -130,7 +147,7 @@ __device__ __forceinline__ void fetch_plane(const Ctx<T, NX>& c, const T* __rest
                                             PlaneRegs<T>& out) {
   using V = typename V2<T>::type;
   const int nx = NX > 0 ? NX : c.nx;
-  const size_t o = static_cast<size_t>(p) * c.P + c.c0;
+  const size_t o = static_cast<size_t>(p) * c.P + c.gc0;
   const size_t om = o + static_cast<size_t>(c.jm) * nx;
   const size_t oo = o + static_cast<size_t>(c.j) * nx;
   const size_t op = o + static_cast<size_t>(c.jp) * nx;
@@ -233,8 +250,8 @@ __device__ __forceinline__ void store_plane(const Ctx<T, NX>& c, int p, const Pl
   // the pair holding column 0 also writes its copy after the row end, the
   // pair holding column nx-1 its copy before column 0; every other thread
   // writes its first value once more onto itself (no branch)
-  const bool hi = c.c0 == nx - 2;
-  const int g = c.c0 == 0 ? nx : (hi ? -1 : c.c0);
+  const bool hi = !Ctx<T, NX>::kSplit && c.c0 == nx - 2;
+  const int g = Ctx<T, NX>::kSplit ? c.c0 : (c.c0 == 0 ? nx : (hi ? -1 : c.c0));
   T* base = c.row(p, 0);
   const int nq = c.r == c.rows - 1 ? 9 : 6;
 #pragma unroll
@@ -254,7 +271,7 @@ __device__ __forceinline__ void fetch_b(const Ctx<T, NX>& c, const T* __restrict
   using V = typename V2<T>::type;
   p = min(max(p, 1), nz - 1);
   const int nx = NX > 0 ? NX : c.nx;
-  const size_t o = static_cast<size_t>(p) * c.P + static_cast<size_t>(c.j) * nx + c.c0;
+  const size_t o = static_cast<size_t>(p) * c.P + static_cast<size_t>(c.j) * nx + c.gc0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) out[k] = NT2<T>::template load<V>(b + k * c.C + o);
 }
@@ -307,7 +324,7 @@ __device__ __forceinline__ void update_phase(const Ctx<T, NX>& c, int p,
   T* own = c.row(p, 3);
   const int W = c.nxp();
   // copy of column 0 after the row end / of column nx-1 before column 0
-  const int g = col == 0 ? nx : (col == nx - 1 ? -1 : col);
+  const int g = Ctx<T, NX>::kSplit ? col : (col == 0 ? nx : (col == nx - 1 ? -1 : col));
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     own[k * W + col] = o[k];
@@ -326,9 +343,9 @@ __device__ __forceinline__ void update_plane(const Ctx<T, NX>& c, int p, int z0,
   update_phase<T, NX, X1>(c, p, bv, cf, oa);
   __syncthreads();
   update_phase<T, NX, 1 - X1>(c, p, bv, cf, ob);
-  if (c.write && p >= z0 && p < z1) {
+  if (c.write && c.own_col && p >= z0 && p < z1) {
     const int nx = NX > 0 ? NX : c.nx;
-    const size_t o = static_cast<size_t>(p) * c.P + static_cast<size_t>(c.j) * nx + c.c0;
+    const size_t o = static_cast<size_t>(p) * c.P + static_cast<size_t>(c.j) * nx + c.gc0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       V v;
@@ -394,10 +411,12 @@ __device__ __forceinline__ void march_step(const Ctx<T, NX>& c, const T* __restr
 }
 
 // threads per workgroup: rows * nx/2, at most 256 except for 768-column rows
-constexpr int sweep_max_threads(int nx) { return nx == 768 ? 384 : 256; }
+// (FP64 rows of 768 are split over two workgroups of 196 threads)
+template <typename T>
+constexpr int sweep_max_threads(int nx) { return nx == 768 && sizeof(T) == 4 ? 384 : 256; }
 
 template <typename T, int NX, int X1, int Z>
-__global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* __restrict__ own_src,
+__global__ __launch_bounds__(sweep_max_threads<T>(NX)) void k_sweep_rows(const T* __restrict__ own_src,
                                                     const T* __restrict__ nbr_src,
                                                     T* __restrict__ dst, const T* __restrict__ b,
                                                     const T* __restrict__ ec,
@@ -406,8 +425,9 @@ __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* _
   extern __shared__ __align__(16) unsigned char smem[];
   // XCD-aware mapping of the (padded) grid onto (row group, segment)
   const int wg = blockIdx.x;
-  const int L = (wg & 7) * a.grid_per_xcd + (wg >> 3);
-  if (L >= a.real_wgs) return;  // whole workgroup leaves before any barrier
+  const int L0 = (wg & 7) * a.grid_per_xcd + (wg >> 3);
+  if (L0 >= a.real_wgs) return;  // whole workgroup leaves before any barrier
+  const int xseg = L0 % a.xs, L = L0 / a.xs;  // the column segments of a row group are neighbours
   int group, sgi;
   if (a.seg_major) {
     sgi = L / a.ngroups;
@@ -420,9 +440,18 @@ __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* _
   c.ring = reinterpret_cast<T*>(smem);
   c.nx = NX > 0 ? NX : a.nx;
   c.rows = a.rows;
-  c.tpr = c.nx >> 1;
+  c.tpr = (Ctx<T, NX>::kSplit ? kSplitW + 2 * kHalo : c.nx) >> 1;
   c.r = threadIdx.x / c.tpr;
   c.c0 = 2 * (threadIdx.x - c.r * c.tpr);
+  if (Ctx<T, NX>::kSplit) {
+    int g = xseg * kSplitW - kHalo + c.c0;
+    g = g < 0 ? g + c.nx : (g >= c.nx ? g - c.nx : g);
+    c.gc0 = g;
+    c.own_col = c.c0 >= kHalo && c.c0 < kHalo + kSplitW;
+  } else {
+    c.gc0 = c.c0;
+    c.own_col = true;
+  }
   // threads = rows * tpr, so every thread has a row slot; rows past the last
   // row of this parity (last group only) are computed on the wrapped row
   // index, which keeps the shared neighbour rows consistent, and not written
@@ -440,7 +469,7 @@ __global__ __launch_bounds__(sweep_max_threads(NX)) void k_sweep_rows(const T* _
     c.nzc = a.nz / 2;
     c.Pc = static_cast<size_t>(nxc) * nyc;
     c.Cc = static_cast<size_t>(c.nzc + 1) * c.Pc;
-    c.I = c.c0 >> 1;
+    c.I = c.gc0 >> 1;
     c.I1 = c.I + 1 == nxc ? 0 : c.I + 1;
     c.JA = Z == 3 ? (c.jm >> 1) : (c.j >> 1);
     c.JB = c.jp >> 1;
@@ -555,6 +584,12 @@ void set_lds_limit_all(int bytes) {
 
 int sweep_rows_per_group(int nx) { return rows_per_group(nx); }
 
+// column segments per row and threads per row of the row sweep
+int column_segments(int nx, int bytes_per_value) { return nx == 768 && bytes_per_value == 8 ? 2 : 1; }
+int threads_per_row(int nx, int bytes_per_value) {
+  return column_segments(nx, bytes_per_value) == 2 ? (kSplitW + 2 * kHalo) / 2 : nx / 2;
+}
+
 template <typename T>
 int blocks_per_cu(Dims d, int threads, size_t lds) {
   int n = 0;
@@ -580,11 +615,11 @@ int sweep_segment_length(Dims d, int bytes_per_value) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
   const int R = rows_per_group(d.nx);
-  const int threads = R * (d.nx / 2);
+  const int threads = R * threads_per_row(d.nx, bytes_per_value);
   const size_t lds = static_cast<size_t>(sweep_lds_bytes(d, bytes_per_value));
   const int per_cu = bytes_per_value == 8 ? blocks_per_cu<double>(d, threads, lds)
                                           : blocks_per_cu<float>(d, threads, lds);
-  const int groups = std::max(1, ((d.ny + 1) / 2 + R - 1) / R);
+  const int groups = std::max(1, ((d.ny + 1) / 2 + R - 1) / R) * column_segments(d.nx, bytes_per_value);
   const int slots = per_cu * cus;
   int nseg = std::max(1, slots / groups);
   // more row groups than resident slots: split z so that the launch is a
@@ -600,7 +635,8 @@ int sweep_segment_length(Dims d, int bytes_per_value) {
 }
 
 int sweep_lds_bytes(Dims d, int bytes_per_value) {
-  return 4 * (2 * rows_per_group(d.nx) + 1) * 3 * (d.nx + 2 * kPad) * bytes_per_value;
+  const int w = column_segments(d.nx, bytes_per_value) == 2 ? kSplitW + 2 * kHalo : d.nx;
+  return 4 * (2 * rows_per_group(d.nx) + 1) * 3 * (w + 2 * kPad) * bytes_per_value;
 }
 
 bool sweep_supported(Dims d, size_t lds_limit, int bytes_per_value) {
@@ -625,10 +661,11 @@ void launch_sweep_half(const T* own_src, const T* nbr_src, T* dst, const T* b, c
   a.rows = rows_per_group(d.nx);
   const int rows = (d.ny - row_par + 1) / 2;
   a.ngroups = (rows + a.rows - 1) / a.rows;
-  a.real_wgs = a.ngroups * a.nseg;
+  a.xs = column_segments(d.nx, sizeof(T));
+  a.real_wgs = a.ngroups * a.nseg * a.xs;
   a.grid_per_xcd = (a.real_wgs + 7) / 8;
   a.seg_major = seg_major;
-  const int threads = a.rows * (d.nx / 2);
+  const int threads = a.rows * threads_per_row(d.nx, sizeof(T));
   const size_t lds = static_cast<size_t>(sweep_lds_bytes(d, sizeof(T)));
   switch (d.nx) {
     case 128: launch_nx<T, 128>(own_src, nbr_src, dst, b, ec, a, cf, zero, threads, lds, s); break;
