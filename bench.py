@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source these counters were taken on.
 SWEEP_COUNTERS = {
     "kernel_source": "paper_1904_03808_amd/csrc/kernels_sweep.hip",
-    "source_sha256_16": "27c8e3129c25ec85",
+    "source_sha256_16": "dea4244a5a0518a8",
     "n": 256,
     "fetch_kib": 177898.6,
     "write_kib": 97920.0,

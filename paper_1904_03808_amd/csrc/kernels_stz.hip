@@ -554,11 +554,20 @@ __global__ __launch_bounds__(256) void k_explicit_velocity(const double* __restr
 // node, kept in registers, so every cell plane is read once per segment.
 __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ sstar,
                                                double* __restrict__ b, int nx, int ny, int nz,
-                                               int seg, double scale) {
+                                               int seg, int blocks, int blocks_per_xcd,
+                                               double scale) {
+  // workgroup w runs on XCD w mod 8; each XCD takes a contiguous range of
+  // column blocks (rows, for 256-wide rows) of one segment after the other, so
+  // the cells of row j-1 that a node of row j reads were just read by the
+  // workgroup of row j-1 on the same XCD and come from its L2
+  const int w = blockIdx.x;
+  const int slot = w >> 3;
+  const int blk = (w & 7) * blocks_per_xcd + slot % blocks_per_xcd;
+  if (blk >= blocks) return;
   const int P = nx * ny;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blk * blockDim.x + threadIdx.x;
   if (t >= P) return;
-  const int k0 = 1 + static_cast<int>(blockIdx.y) * seg;
+  const int k0 = 1 + (slot / blocks_per_xcd) * seg;
   if (k0 > nz - 1) return;
   const int k1 = min(k0 + seg, nz);  // nodes k0 .. k1-1
   const int i = t % nx, j = t / nx;
@@ -904,8 +913,9 @@ void launch_rhs(const double* sstar, double* b, Dims d, double h, double dt, hip
   int seg = 16;
   while (seg > 1 && wgs * ((interior + seg - 1) / seg) < 2048) seg /= 2;
   const int nseg = (interior + seg - 1) / seg;
-  hipLaunchKernelGGL(k_rhs, dim3(wgs, nseg), dim3(256), 0, s, sstar, b, d.nx, d.ny, d.nz, seg,
-                     0.25 / (h * dt));
+  const int bpx = (wgs + 7) / 8;
+  hipLaunchKernelGGL(k_rhs, dim3(8 * bpx * nseg), dim3(256), 0, s, sstar, b, d.nx, d.ny, d.nz, seg,
+                     wgs, bpx, 0.25 / (h * dt));
   hipLaunchKernelGGL(k_zero_walls, dim3(blocks_for(6LL * d.plane(), 256)), dim3(256), 0, s, b,
                      d.nx, d.ny, d.nz);
 }
