@@ -148,7 +148,7 @@ qs_status qs_apply(qs_handle* hd, const double* x, double* y);
  * ||b_eff - K x||_2 <= rtol ||b_eff||_2 (b_eff = b - K_IB x_B, 2-norm over
  * the 3 nx ny (nz-1) interior unknowns), checked before each cycle (FP64) or
  * before each refinement step (FP32_IR: the FP64 residual, scaled, is the
- * right-hand side of up to four FP32 V-cycles, fewer when the last step's
+ * right-hand side of up to six FP32 V-cycles, fewer when the last step's
  * contraction says fewer reach rtol; cycles counts V-cycles).
  * x: in = initial guess with the wall velocities in planes 0 and nz (never
  * written); out = solution.  Wall planes of b are ignored.  rtol <= 0 runs

@@ -641,7 +641,7 @@ static qs_status solve_impl(qs_handle* hd, const double* b, double* x, double rt
   // FP32-IR: each refinement step runs up to kMaxInner FP32 V-cycles on the
   // scaled residual before the next FP64 residual, fewer when the contraction
   // per V-cycle seen in the previous step says fewer reach rtol.
-  constexpr int kMaxInner = 4;
+  constexpr int kMaxInner = 6;
   double rel_prev = 0.0;
   int inner_prev = 0;
   for (;;) {

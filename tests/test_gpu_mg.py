@@ -143,9 +143,10 @@ def test_coarse_solve(n):
     assert rel(host(xd), x) < 1e-12
 
 
-@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("n", GRIDS + [(64, 64, 64)])
 def test_vcycle_iterates(n):
-    """GPU iterates after each of the first 5 V-cycles match the oracle's (<= 1e-12)."""
+    """GPU iterates after each of the first 5 V-cycles match the oracle's (<= 1e-12);
+    64^3 runs four levels, with colour pairs on 32^3 and 16^3."""
     rng = np.random.default_rng(5)
     g, o = make(*n)
     b = rand_node(rng, *n)
