@@ -430,19 +430,36 @@ __global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __
   cell_velocity(v, nx, ny, nz, c, u);
   // the six advection terms, one component at a time (a loop that is not
   // unrolled keeps one copy of the stencil code and few registers), parked in
-  // LDS slots of this thread until the update writes each component
+  // LDS slots of this thread until the update writes each component; the 13
+  // values of the next component are loaded while one component is computed
   __shared__ double advs[6][kTile * kTile];
   const double ih2 = 1.0 / (2.0 * a.h);
+  // the 13 values of component n: centre, 4 along x, 4 along y, 4 along z
+  auto fetch = [&](int n, double w[13]) {
+    const double* f = sigma + n * N + t;
+    const double* g = sigma + n * N;
+    w[0] = f[0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      w[1 + q] = f[xo[q]];
+      w[5 + q] = f[yo[q]];
+    }
+    const int ks[4] = {k - 2, k - 1, k + 1, k + 2};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[9 + q] = z_layer(g, P, nz, col, ks[q]);
+  };
+  double cur[13], nxt[13];
+  fetch(0, cur);
 #pragma unroll 1
   for (int n = 0; n < 6; ++n) {
-    const double* f = sigma + n * N + t;
-    const double f0 = f[0];
-    const double dx = eno_2h(f[xo[0]], f[xo[1]], f0, f[xo[2]], f[xo[3]], u[0]);
-    const double dy = eno_2h(f[yo[0]], f[yo[1]], f0, f[yo[2]], f[yo[3]], u[1]);
-    const double* g = sigma + n * N;
-    const double dz = eno_2h(z_layer(g, P, nz, col, k - 2), z_layer(g, P, nz, col, k - 1), f0,
-                             z_layer(g, P, nz, col, k + 1), z_layer(g, P, nz, col, k + 2), u[2]);
+    if (n < 5) fetch(n + 1, nxt);  // in flight while component n is computed
+    const double dx = eno_2h(cur[1], cur[2], cur[0], cur[3], cur[4], u[0]);
+    const double dy = eno_2h(cur[5], cur[6], cur[0], cur[7], cur[8], u[1]);
+    const double dz = eno_2h(cur[9], cur[10], cur[0], cur[11], cur[12], u[2]);
     advs[n][threadIdx.x] = (u[0] * dx + u[1] * dy + u[2] * dz) * ih2;
+    if (n < 5)
+#pragma unroll
+      for (int q = 0; q < 13; ++q) cur[q] = nxt[q];
   }
   load_voigt(sigma, N, t, S);
   stz_update<DIFF, true>(sigma, chi, sstar, chi1, Dcell, nx, ny, nz, c, t, L, S, chi[t],
