@@ -380,16 +380,15 @@ __device__ __forceinline__ double z_layer(const double* __restrict__ f, int P, i
 
 // With the advection of the stress (Eq. sig_star_evol): one thread per cell,
 // a workgroup per 16 x 16 tile of one cell plane.  Eq. ENO reads two cells on
-// each side along x, y and z, so the mapping keeps those reads in cache: a
-// band of 16 rows (all tiles along x, so the x wrap stays inside it) goes to
-// one XCD (workgroup w runs on XCD w mod 8), whose workgroups take the band
-// plane after plane and tile after tile.  The planes k-2 .. k+2 of a band are
-// then in flight together and share that XCD's L2, and only the two rows on
-// each side of the band come from elsewhere.  Each derivative is Eq. ENO along its axis (x and y
-// wrap; in z the layers past the walls continue the two nearest layers
-// linearly, Sec. 3.5), with u the mean of the cell's eight corner velocities;
-// no fused multiply-adds here, so the branch choices of Eq. ENO are taken on
-// the same FP64 values as the oracle's.
+// each side along x, y and z; x and y come from the tile staged in LDS, and
+// the mapping keeps the z reads in cache: a band of 16 rows (all tiles along
+// x) goes to one XCD (workgroup w runs on XCD w mod 8), whose workgroups take
+// the band plane after plane and tile after tile.  The planes k-2 .. k+2 of a
+// band are then in flight together and share that XCD's L2.  Each derivative
+// is Eq. ENO along its axis (x and y wrap; in z the layers past the walls
+// continue the two nearest layers linearly, Sec. 3.5), with u the mean of the
+// cell's eight corner velocities; no fused multiply-adds here, so the branch
+// choices of Eq. ENO are taken on the same FP64 values as the oracle's.
 constexpr int kTile = 16;
 
 template <bool DIFF>
@@ -409,58 +408,73 @@ __global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __
   if (band >= bands) return;
   const int r = slot - (slot / per_band) * per_band;
   const int k = r / ntx, tx = r - k * ntx;
+  const int lx = static_cast<int>(threadIdx.x) % kTile, ly = static_cast<int>(threadIdx.x) / kTile;
+  const int i0 = tx * kTile, j0 = band * kTile;
+  // cells past the grid edge (ragged last tile) compute on a clamped cell and
+  // write nothing; they take part in the staging and the barriers
+  const bool active = i0 + lx < nx && j0 + ly < ny;
   CellIdx c;
-  c.i = tx * kTile + static_cast<int>(threadIdx.x) % kTile;
-  c.j = band * kTile + static_cast<int>(threadIdx.x) / kTile;
-  if (c.i >= nx || c.j >= ny) return;
+  c.i = min(i0 + lx, nx - 1);
+  c.j = min(j0 + ly, ny - 1);
   c.k = k;
   c.ip = c.i + 1 == nx ? 0 : c.i + 1;
   c.jp = c.j + 1 == ny ? 0 : c.j + 1;
   const int P = nx * ny, N = P * nz;
   const int col = c.j * nx + c.i;
   const int t = k * P + col;
-  const int im1 = c.i == 0 ? nx - 1 : c.i - 1, im2 = im1 == 0 ? nx - 1 : im1 - 1;
-  const int ip2 = c.ip + 1 == nx ? 0 : c.ip + 1;
-  const int jm1 = c.j == 0 ? ny - 1 : c.j - 1, jm2 = jm1 == 0 ? ny - 1 : jm1 - 1;
-  const int jp2 = c.jp + 1 == ny ? 0 : c.jp + 1;
-  const int xo[4] = {im2 - c.i, im1 - c.i, c.ip - c.i, ip2 - c.i};
-  const int yo[4] = {(jm2 - c.j) * nx, (jm1 - c.j) * nx, (c.jp - c.j) * nx, (jp2 - c.j) * nx};
   double L[3][3], S[3][3], u[3];
   cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
   cell_velocity(v, nx, ny, nz, c, u);
-  // the six advection terms, one component at a time (a loop that is not
+  // The six advection terms, one component at a time (a loop that is not
   // unrolled keeps one copy of the stencil code and few registers), parked in
-  // LDS slots of this thread until the update writes each component; the 13
-  // values of the next component are loaded while one component is computed
+  // LDS slots of this thread until the update writes each component.  The
+  // component's plane k over the tile and two cells around it (x and y wrap)
+  // is staged in LDS, so each value is loaded once instead of by the five
+  // cells that use it; the four z neighbours of the cell's own column come
+  // from memory.  The next component's values are loaded while one is
+  // computed.
+  constexpr int kW = kTile + 4;  // staged rows and columns
   __shared__ double advs[6][kTile * kTile];
+  __shared__ double tl[kW][kW + 1];
   const double ih2 = 1.0 / (2.0 * a.h);
-  // the 13 values of component n: centre, 4 along x, 4 along y, 4 along z
-  auto fetch = [&](int n, double w[13]) {
-    const double* f = sigma + n * N + t;
-    const double* g = sigma + n * N;
-    w[0] = f[0];
+  int soff[2];  // plane offsets of this thread's two staged cells (the second may be unused)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      w[1 + q] = f[xo[q]];
-      w[5 + q] = f[yo[q]];
-    }
+  for (int q = 0; q < 2; ++q) {
+    const int e = min(static_cast<int>(threadIdx.x) + q * kTile * kTile, kW * kW - 1);
+    const int sy = e / kW, sx = e - sy * kW;
+    const int gj = ((j0 - 2 + sy) % ny + ny) % ny, gi = ((i0 - 2 + sx) % nx + nx) % nx;
+    soff[q] = gj * nx + gi;
+  }
+  const bool second = static_cast<int>(threadIdx.x) + kTile * kTile < kW * kW;
+  auto fetch = [&](int n, double sv[2], double zv[4]) {
+    const double* g = sigma + n * N;
+    sv[0] = g[k * P + soff[0]];
+    sv[1] = g[k * P + soff[1]];
     const int ks[4] = {k - 2, k - 1, k + 1, k + 2};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) w[9 + q] = z_layer(g, P, nz, col, ks[q]);
+    for (int q = 0; q < 4; ++q) zv[q] = z_layer(g, P, nz, col, ks[q]);
   };
-  double cur[13], nxt[13];
-  fetch(0, cur);
+  double sv[2], zv[4];
+  fetch(0, sv, zv);
 #pragma unroll 1
   for (int n = 0; n < 6; ++n) {
-    if (n < 5) fetch(n + 1, nxt);  // in flight while component n is computed
-    const double dx = eno_2h(cur[1], cur[2], cur[0], cur[3], cur[4], u[0]);
-    const double dy = eno_2h(cur[5], cur[6], cur[0], cur[7], cur[8], u[1]);
-    const double dz = eno_2h(cur[9], cur[10], cur[0], cur[11], cur[12], u[2]);
-    advs[n][threadIdx.x] = (u[0] * dx + u[1] * dy + u[2] * dz) * ih2;
-    if (n < 5)
+    __syncthreads();  // the previous component's reads of tl are done
+    tl[threadIdx.x / kW][threadIdx.x % kW] = sv[0];
+    if (second) tl[(threadIdx.x + kTile * kTile) / kW][(threadIdx.x + kTile * kTile) % kW] = sv[1];
+    double z[4];
 #pragma unroll
-      for (int q = 0; q < 13; ++q) cur[q] = nxt[q];
+    for (int q = 0; q < 4; ++q) z[q] = zv[q];
+    __syncthreads();
+    if (n < 5) fetch(n + 1, sv, zv);  // in flight while component n is computed
+    const double* row = &tl[ly + 2][lx + 2];
+    const double f0 = row[0];
+    const double dx = eno_2h(row[-2], row[-1], f0, row[1], row[2], u[0]);
+    const double dy = eno_2h(tl[ly][lx + 2], tl[ly + 1][lx + 2], f0, tl[ly + 3][lx + 2],
+                             tl[ly + 4][lx + 2], u[1]);
+    const double dz = eno_2h(z[0], z[1], f0, z[2], z[3], u[2]);
+    advs[n][threadIdx.x] = (u[0] * dx + u[1] * dy + u[2] * dz) * ih2;
   }
+  if (!active) return;
   load_voigt(sigma, N, t, S);
   stz_update<DIFF, true>(sigma, chi, sstar, chi1, Dcell, nx, ny, nz, c, t, L, S, chi[t],
                          [&](int n) { return advs[n][threadIdx.x]; }, a);
