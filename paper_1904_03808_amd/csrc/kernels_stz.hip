@@ -30,10 +30,10 @@ __device__ __forceinline__ bool cell_of(int t, int nx, int ny, int nz, CellIdx* 
 
 // Velocity gradient L[a][b] = d v_a / d x_b at a cell centre: the average of
 // the four edge differences parallel to x_b (Eq. stag_stenc).
-__device__ __forceinline__ void cell_gradient(const double* __restrict__ v, int nx, int ny, int nz,
-                                              const CellIdx& c, double ih4, double L[3][3]) {
-  const int P = nx * ny, C = (nz + 1) * P;
-  const int xs[2] = {c.i, c.ip}, ys[2] = {c.j, c.jp};
+// Velocity gradient of a cell from its eight corner nodes, get(a, dz, dy, dx)
+// returning component a at corner (dz, dy, dx).
+template <typename G>
+__device__ __forceinline__ void cell_gradient_from(G get, double ih4, double L[3][3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double f[2][2][2];
@@ -42,7 +42,7 @@ __device__ __forceinline__ void cell_gradient(const double* __restrict__ v, int 
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) f[dz][dy][dx] = v[a * C + (c.k + dz) * P + ys[dy] * nx + xs[dx]];
+        for (int dx = 0; dx < 2; ++dx) f[dz][dy][dx] = get(a, dz, dy, dx);
     double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -56,6 +56,15 @@ __device__ __forceinline__ void cell_gradient(const double* __restrict__ v, int 
     L[a][1] = gy * ih4;
     L[a][2] = gz * ih4;
   }
+}
+
+__device__ __forceinline__ void cell_gradient(const double* __restrict__ v, int nx, int ny, int nz,
+                                              const CellIdx& c, double ih4, double L[3][3]) {
+  const int P = nx * ny, C = (nz + 1) * P;
+  const int xs[2] = {c.i, c.ip}, ys[2] = {c.j, c.jp};
+  cell_gradient_from(
+      [&](int a, int dz, int dy, int dx) { return v[a * C + (c.k + dz) * P + ys[dy] * nx + xs[dx]]; },
+      ih4, L);
 }
 
 __device__ __forceinline__ void load_voigt(const double* __restrict__ s, int N, int o, double S[3][3]) {
@@ -88,10 +97,9 @@ __device__ __forceinline__ Plastic plastic_rate(double sbar, double chi, const S
 }
 
 // Velocity at the cell centre: the mean of the cell's eight corner nodes.
-__device__ __forceinline__ void cell_velocity(const double* __restrict__ v, int nx, int ny, int nz,
-                                              const CellIdx& c, double u[3]) {
-  const int P = nx * ny, C = (nz + 1) * P;
-  const int xs[2] = {c.i, c.ip}, ys[2] = {c.j, c.jp};
+// Mean of the eight corner velocities of a cell (get as for cell_gradient_from).
+template <typename G>
+__device__ __forceinline__ void cell_velocity_from(G get, double u[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double acc = 0.0;
@@ -100,7 +108,7 @@ __device__ __forceinline__ void cell_velocity(const double* __restrict__ v, int 
 #pragma unroll
       for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) acc += v[a * C + (c.k + dz) * P + ys[dy] * nx + xs[dx]];
+        for (int dx = 0; dx < 2; ++dx) acc += get(a, dz, dy, dx);
     u[a] = acc / 8.0;
   }
 }
@@ -422,9 +430,6 @@ __global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __
   const int P = nx * ny, N = P * nz;
   const int col = c.j * nx + c.i;
   const int t = k * P + col;
-  double L[3][3], S[3][3], u[3];
-  cell_gradient(v, nx, ny, nz, c, 0.25 / a.h, L);
-  cell_velocity(v, nx, ny, nz, c, u);
   // The six advection terms, one component at a time (a loop that is not
   // unrolled keeps one copy of the stencil code and few registers), parked in
   // LDS slots of this thread until the update writes each component.  The
@@ -432,20 +437,27 @@ __global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __
   // is staged in LDS, so each value is loaded once instead of by the five
   // cells that use it; the four z neighbours of the cell's own column come
   // from memory.  The next component's values are loaded while one is
-  // computed.
+  // computed.  Before that, the tile's corner nodes (17 x 17 columns, node
+  // planes k and k+1) pass through the same LDS as advs and fcell, so each
+  // node is loaded once instead of by the eight cells around it.
   constexpr int kW = kTile + 4;  // staged rows and columns
-  __shared__ double advs[6][kTile * kTile];
+  constexpr int kT = kTile * kTile;
+  __shared__ double pool[2 * 6 * kT];
+  double(*advs)[kT] = reinterpret_cast<double(*)[kT]>(pool);
+  double(*fcell)[kT] = reinterpret_cast<double(*)[kT]>(pool + 6 * kT);  // the cell's own sigma
+  double(*vt)[2][kTile + 1][kTile + 2] = reinterpret_cast<double(*)[2][kTile + 1][kTile + 2]>(pool);
+  static_assert(3 * 2 * (kTile + 1) * (kTile + 2) <= 2 * 6 * kT, "corner nodes fit the pool");
   __shared__ double tl[kW][kW + 1];
   const double ih2 = 1.0 / (2.0 * a.h);
   int soff[2];  // plane offsets of this thread's two staged cells (the second may be unused)
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    const int e = min(static_cast<int>(threadIdx.x) + q * kTile * kTile, kW * kW - 1);
+    const int e = min(static_cast<int>(threadIdx.x) + q * kT, kW * kW - 1);
     const int sy = e / kW, sx = e - sy * kW;
     const int gj = ((j0 - 2 + sy) % ny + ny) % ny, gi = ((i0 - 2 + sx) % nx + nx) % nx;
     soff[q] = gj * nx + gi;
   }
-  const bool second = static_cast<int>(threadIdx.x) + kTile * kTile < kW * kW;
+  const bool second = static_cast<int>(threadIdx.x) + kT < kW * kW;
   auto fetch = [&](int n, double sv[2], double zv[4]) {
     const double* g = sigma + n * N;
     sv[0] = g[k * P + soff[0]];
@@ -456,11 +468,38 @@ __global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __
   };
   double sv[2], zv[4];
   fetch(0, sv, zv);
+  {
+    constexpr int kNodes = 3 * 2 * (kTile + 1) * (kTile + 1);
+    constexpr int kPer = (kNodes + kT - 1) / kT;
+    double nv[kPer];
+    int comp[kPer], dz[kPer], yy[kPer], xx[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = min(static_cast<int>(threadIdx.x) + q * kT, kNodes - 1);
+      comp[q] = e / (2 * (kTile + 1) * (kTile + 1));
+      const int rem = e - comp[q] * 2 * (kTile + 1) * (kTile + 1);
+      dz[q] = rem / ((kTile + 1) * (kTile + 1));
+      const int rem2 = rem - dz[q] * (kTile + 1) * (kTile + 1);
+      yy[q] = rem2 / (kTile + 1);
+      xx[q] = rem2 - yy[q] * (kTile + 1);
+      const int gi = (i0 + xx[q]) % nx, gj = (j0 + yy[q]) % ny;
+      nv[q] = v[comp[q] * (nz + 1) * P + (k + dz[q]) * P + gj * nx + gi];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q)
+      if (static_cast<int>(threadIdx.x) + q * kT < kNodes) vt[comp[q]][dz[q]][yy[q]][xx[q]] = nv[q];
+  }
+  __syncthreads();
+  const int ci = c.i - i0, cj = c.j - j0;  // the cell within the tile (clamped cells included)
+  auto corner = [&](int cmp, int ez, int ey, int ex) { return vt[cmp][ez][cj + ey][ci + ex]; };
+  double L[3][3], S[3][3], u[3];
+  cell_gradient_from(corner, 0.25 / a.h, L);
+  cell_velocity_from(corner, u);
 #pragma unroll 1
   for (int n = 0; n < 6; ++n) {
-    __syncthreads();  // the previous component's reads of tl are done
+    __syncthreads();  // the previous component's reads of tl (at n = 0: of the corner nodes) are done
     tl[threadIdx.x / kW][threadIdx.x % kW] = sv[0];
-    if (second) tl[(threadIdx.x + kTile * kTile) / kW][(threadIdx.x + kTile * kTile) % kW] = sv[1];
+    if (second) tl[(threadIdx.x + kT) / kW][(threadIdx.x + kT) % kW] = sv[1];
     double z[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) z[q] = zv[q];
@@ -473,9 +512,15 @@ __global__ __launch_bounds__(kTile * kTile) void k_stz_step_adv(const double* __
                              tl[ly + 4][lx + 2], u[1]);
     const double dz = eno_2h(z[0], z[1], f0, z[2], z[3], u[2]);
     advs[n][threadIdx.x] = (u[0] * dx + u[1] * dy + u[2] * dz) * ih2;
+    fcell[n][threadIdx.x] = f0;
   }
   if (!active) return;
-  load_voigt(sigma, N, t, S);
+#pragma unroll
+  for (int n = 0; n < 6; ++n) {
+    const double val = fcell[n][threadIdx.x];
+    S[VA[n]][VB[n]] = val;
+    S[VB[n]][VA[n]] = val;
+  }
   stz_update<DIFF, true>(sigma, chi, sstar, chi1, Dcell, nx, ny, nz, c, t, L, S, chi[t],
                          [&](int n) { return advs[n][threadIdx.x]; }, a);
 }
