@@ -120,11 +120,12 @@ def test_stz_step_with_plastic_substeps(n, n_sub, dt):
     assert rel(rs, r1) > 1e-6
 
 
-@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20), (12, 10, 2)])
+@pytest.mark.parametrize("n", [(16, 16, 16), (24, 20, 20), (12, 10, 2), (20, 18, 5)])
 def test_stz_step_with_advection(n):
     """The advection term -(v . grad) sigma with Eq. ENO (x, y wrap, two
     extrapolated ghost layers in z; nz = 2 puts both walls' ghosts into every
-    stencil) matches the oracle's, alone, together with chi diffusion and
+    stencil, an odd nz leaves half of the last plane pair past the grid, and
+    20 x 18 leaves ragged tiles) matches the oracle's, alone, together with chi diffusion and
     per-cell plastic sub-steps, and with the backward-Euler update; the curvature tests that pick each branch are
     taken on identical FP64 values on both sides."""
     rng = np.random.default_rng(6)
