@@ -13,6 +13,7 @@
 
 #include "device.h"
 #include "hierarchy.h"
+#include "packed_stencil.h"
 #include "qsmg.h"
 
 using namespace qs;
@@ -37,6 +38,8 @@ struct LevelBufs {
   double* D64 = nullptr;
   float* S32 = nullptr;
   float* D32 = nullptr;
+  double* P64 = nullptr;  // packed plane stencils (packed_stencil.h)
+  float* P32 = nullptr;
 };
 
 // Assigns aligned sub-buffers of the workspace; with base == nullptr it only
@@ -89,8 +92,6 @@ struct qs_handle {
   FineCoef<float> fc32;
   double* Ainv = nullptr;
   int ncoarse = 0;
-  double* ctin = nullptr;
-  double* ctout = nullptr;
   double* partial = nullptr;
   int partial_n = 0;
   double* dnorm = nullptr;   // device, 4 doubles
@@ -133,6 +134,8 @@ void carve(const qs_params* p, const std::vector<int>& dims, char* base, qs_hand
     lb.D64 = cv.take<double>(planes * 9);
     lb.S32 = cv.take<float>(planes * kStencil);
     lb.D32 = cv.take<float>(planes * 9);
+    lb.P64 = cv.take<double>(planes * kPackedStencil);
+    lb.P32 = cv.take<float>(planes * kPackedStencil);
     const int nb = residual_blocks(lb.d);
     if (nb > maxblocks) maxblocks = nb;
     if (hd) hd->L[l] = lb;
@@ -140,16 +143,12 @@ void carve(const qs_params* p, const std::vector<int>& dims, char* base, qs_hand
   const Dims g{dims[3 * (nlev - 1)], dims[3 * (nlev - 1) + 1], dims[3 * (nlev - 1) + 2]};
   const int nc = 3 * g.nx * g.ny * (g.nz - 1);
   double* Ainv = cv.take<double>(static_cast<size_t>(nc) * nc);
-  double* ctin = cv.take<double>(nc);
-  double* ctout = cv.take<double>(nc);
   double* partial = cv.take<double>(maxblocks);
   double* dnorm = cv.take<double>(4);
   if (hd) {
     hd->nlev = nlev;
     hd->ncoarse = nc;
     hd->Ainv = Ainv;
-    hd->ctin = ctin;
-    hd->ctout = ctout;
     hd->partial = partial;
     hd->partial_n = maxblocks;
     hd->dnorm = dnorm;
@@ -162,6 +161,39 @@ thread_local char g_last_error[256] = "";
 qs_status hip_fail(const char* what, hipError_t e) {
   std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s", what, hipGetErrorString(e));
   return QS_ERR_HIP;
+}
+
+void set_error(const char* what) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", what); }
+
+// Packs the plane stencils of one level (packed_stencil.h).  Returns false if
+// an entry that the packing leaves out (it vanishes by the reflection
+// symmetry of the operator) exceeds 1e-12 of the largest entry of the level.
+bool pack_level(const HostLevel& hl, std::vector<double>* out) {
+  const int planes = hl.nz + 1;
+  out->assign(static_cast<size_t>(planes) * kPackedStencil, 0.0);
+  double big = 0.0, left_out = 0.0;
+  for (int k = 0; k < planes; ++k) {
+    const double* S = hl.stencil.data() + static_cast<size_t>(k) * kStencil;
+    double* P = out->data() + static_cast<size_t>(k) * kPackedStencil;
+    int n = 0;
+    for (int oz = 0; oz < 3; ++oz)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int ox = 0; ox < 3; ++ox)
+          for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) {
+              const double v = S[(oz * 9 + oy * 3 + ox) * 9 + c * 3 + d];
+              big = std::max(big, std::fabs(v));
+              const bool centre = oz == 1 && oy == 1 && ox == 1;
+              if (centre && c == d)
+                P[kPackedCentre + c] = v;
+              else if (!centre && packed_used(oz, oy, ox, c, d))
+                P[n++] = v;
+              else
+                left_out = std::max(left_out, std::fabs(v));
+            }
+    for (int e = 0; e < 9; ++e) P[kPackedInv + e] = hl.dinv[static_cast<size_t>(k) * 9 + e];
+  }
+  return left_out <= 1e-12 * big;
 }
 
 #define QS_HIP(call)                                   \
@@ -202,6 +234,7 @@ struct Prec<double> {
   static double* y(LevelBufs& l) { return l.y64; }
   static const double* S(LevelBufs& l) { return l.S64; }
   static const double* D(LevelBufs& l) { return l.D64; }
+  static const double* Pk(LevelBufs& l) { return l.P64; }
   static const FineCoef<double>& fc(qs_handle* hd) { return hd->fc64; }
   static int seg(const LevelBufs& l) { return l.seg64; }
 };
@@ -213,6 +246,7 @@ struct Prec<float> {
   static float* y(LevelBufs& l) { return l.y32; }
   static const float* S(LevelBufs& l) { return l.S32; }
   static const float* D(LevelBufs& l) { return l.D32; }
+  static const float* Pk(LevelBufs& l) { return l.P32; }
   static const FineCoef<float>& fc(qs_handle* hd) { return hd->fc32; }
   static int seg(const LevelBufs& l) { return l.seg32; }
 };
@@ -239,9 +273,9 @@ void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_inte
     launch_residual_fine<T, T>(x, b, r, lb.d, hd->fc64, 1.0, zero_interior, nullptr, hd->stream);
   else if (sizeof(T) == 8 && !zero_interior && lb.d.nx % 2 == 0 && aligned16(x) && aligned16(b) &&
            aligned16(r))  // FP64: 56 against 88 us at 128^3; FP32 is faster one node per thread
-    launch_residual_pair_gen<T>(x, b, r, lb.d, Prec<T>::S(lb), hd->stream);
+    launch_residual_pair_gen<T>(x, b, r, lb.d, Prec<T>::Pk(lb), hd->stream);
   else
-    launch_residual_gen<T>(x, b, r, lb.d, Prec<T>::S(lb), zero_interior, nullptr, hd->stream);
+    launch_residual_gen<T>(x, b, r, lb.d, Prec<T>::Pk(lb), zero_interior, nullptr, hd->stream);
 }
 
 // Coarsest level: x_interior = A^{-1} (b - A_IB x_B).  Only the FP64 fine
@@ -255,7 +289,7 @@ void coarse_solve(qs_handle* hd, int l, T* x, const T* b, T* tmp) {
     residual<T>(hd, l, x, b, tmp, true);
     rhs = tmp;
   }
-  launch_coarse_solve<T>(hd->Ainv, hd->ncoarse, rhs, x, lb.d, hd->ctin, hd->ctout, hd->stream);
+  launch_coarse_solve<T>(hd->Ainv, hd->ncoarse, rhs, x, lb.d, hd->stream);
 }
 
 // Copy the two wall planes of x into y (both buffers must carry them).
@@ -309,7 +343,7 @@ void smooth(qs_handle* hd, int l, T* x, const T* b, int sweeps, bool reverse,
       for (int q = 0; q < 8; ++q) {
         const int c = ord[reverse ? 7 - q : q];
         if (pairs && q % 2 == 0 && ord[reverse ? 6 - q : q + 1] == (c ^ 1)) {
-          launch_colour_pair_gen<T>(x, b, lb.d, c, Prec<T>::S(lb), Prec<T>::D(lb), hd->stream);
+          launch_colour_pair_gen<T>(x, b, lb.d, c, Prec<T>::Pk(lb), hd->stream);
           ++q;
           continue;
         }
@@ -540,7 +574,9 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
   // upload stencils (FP64 and their FP32 roundings) and the coarse inverse;
   // the staging vectors live until the synchronisation below
   std::vector<std::vector<float>> stage32;
-  stage32.reserve(2 * hd->nlev);
+  std::vector<std::vector<double>> stage64;
+  stage32.reserve(3 * hd->nlev);
+  stage64.reserve(hd->nlev);
   qs_status st = QS_OK;
   for (int l = 0; l < hd->nlev && st == QS_OK; ++l) {
     const HostLevel& hl = H.levels[l];
@@ -549,6 +585,15 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
     const std::vector<float>& s32 = stage32.back();
     stage32.emplace_back(hl.dinv.begin(), hl.dinv.end());
     const std::vector<float>& d32 = stage32.back();
+    stage64.emplace_back();
+    if (!pack_level(hl, &stage64.back())) {
+      set_error("setup: a stencil entry that vanishes by symmetry is not negligible");
+      st = QS_ERR_ARG;
+      break;
+    }
+    const std::vector<double>& p64 = stage64.back();
+    stage32.emplace_back(p64.begin(), p64.end());
+    const std::vector<float>& p32 = stage32.back();
     hipError_t e = hipMemcpyAsync(lb.S64, hl.stencil.data(), hl.stencil.size() * 8,
                                   hipMemcpyHostToDevice, hd->stream);
     if (e == hipSuccess)
@@ -558,6 +603,10 @@ qs_status qs_setup(const qs_params* p, void* workspace, size_t workspace_bytes, 
       e = hipMemcpyAsync(lb.S32, s32.data(), s32.size() * 4, hipMemcpyHostToDevice, hd->stream);
     if (e == hipSuccess)
       e = hipMemcpyAsync(lb.D32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice, hd->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(lb.P64, p64.data(), p64.size() * 8, hipMemcpyHostToDevice, hd->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(lb.P32, p32.data(), p32.size() * 4, hipMemcpyHostToDevice, hd->stream);
     if (e != hipSuccess) st = hip_fail("hipMemcpyAsync (stencil upload)", e);
   }
   if (st == QS_OK) {
@@ -973,8 +1022,7 @@ qs_status qs_coarse_solve(qs_handle* hd, double* x, const double* b) {
   const int l = hd->nlev - 1;
   LevelBufs& lb = hd->L[l];
   residual<double>(hd, l, x, b, lb.r64, true);
-  launch_coarse_solve<double>(hd->Ainv, hd->ncoarse, lb.r64, x, lb.d, hd->ctin, hd->ctout,
-                              hd->stream);
+  launch_coarse_solve<double>(hd->Ainv, hd->ncoarse, lb.r64, x, lb.d, hd->stream);
   return launch_check();
 }
 

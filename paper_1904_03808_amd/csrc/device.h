@@ -57,15 +57,15 @@ template <typename T>
 void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
                        hipStream_t s);
 // Colours c and c ^ 1 (c first) in one launch on a level with the generic
-// stencil; needs an even row length of at most 512.
+// stencil, given in packed form (packed_stencil.h); needs an even row length
+// of at most 512.
 template <typename T>
-void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
-                            hipStream_t s);
+void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* Pst, hipStream_t s);
 bool colour_pair_supported(Dims d);
 // Coarse residual r = b - A x on the interior, two nodes per thread (even nx,
-// 16-byte aligned vectors).
+// 16-byte aligned vectors), packed stencil.
 template <typename T>
-void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* S, hipStream_t s);
+void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* Pst, hipStream_t s);
 
 // Fine-level row-parity half sweep (kernels_sweep.hip): updates every node
 // of the rows with parity row_par, reading own rows from own_src, neighbour
@@ -94,7 +94,7 @@ template <typename Tin, typename Tout>
 int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const FineCoef<double>& c,
                          double out_scale, bool zero_interior, double* partial, hipStream_t s);
 template <typename T>
-int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool zero_interior,
+int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* Pst, bool zero_interior,
                         double* partial, hipStream_t s);
 int residual_blocks(Dims d);  // upper bound on the partial sums any residual kernel writes
 
@@ -136,10 +136,10 @@ void launch_fill(T* x, size_t n, T value, hipStream_t s);
 template <typename T>
 void launch_zero_interior(T* x, Dims d, hipStream_t s);
 
-// Coarsest level: x_interior = Ainv * gather(b), computed in double.
+// Coarsest level: x_interior = Ainv b_interior, computed in double in one
+// launch (interior unknowns ordered by component, plane, row, column).
 template <typename T>
-void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, double* tmp_in,
-                         double* tmp_out, hipStream_t s);
+void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, hipStream_t s);
 
 // --- STZ / projection kernels (kernels_stz.hip) -----------------------------
 struct StzArgs {

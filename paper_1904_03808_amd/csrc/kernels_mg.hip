@@ -9,8 +9,10 @@
 // 4(k&1).  Nodes of one colour are never coupled by the 3x3x3 stencil, so a
 // colour pass updates them in place in any order without races.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.h"
+#include "packed_stencil.h"
 
 namespace qs {
 
@@ -95,82 +97,24 @@ __global__ __launch_bounds__(256) void k_colour_fine(T* __restrict__ x, const T*
   for (int c = 0; c < 3; ++c) x[c * n.C + o] = v[c];
 }
 
-// Generic per-plane 27-point block stencil S[k][o][c][d].
-// Plane k's 243 stencil entries followed by its 9 inverse-centre entries,
-// copied into LDS by every thread of the block (one load each, issued before
-// the neighbour loads so that waiting for them does not wait for those).
-// Blocks of 64 threads take four entries each: all loads are issued before
-// the first store, so a thread waits for one round of memory latency.
-template <typename T>
-__device__ __forceinline__ void stage_stencil_inverse(T* sc, const T* __restrict__ S,
-                                                      const T* __restrict__ Dinv, int k) {
-  T v[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
-    v[u] = e < 243 ? S[static_cast<size_t>(k) * 243 + e]
-                   : (e < 252 ? Dinv[static_cast<size_t>(k) * 9 + e - 243] : T(0));
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
-    if (e < 252) sc[e] = v[u];
-  }
-}
-
-// The same entries with each row (oz, y) of 27 padded to 28, so that a row
-// starts on a 16-byte boundary: S[k][oz][y][q][c][d] -> sc[(3 oz + y) 28 +
-// 9 q + 3 c + d], D^-1 at sc[252] (when Dinv is given).
-template <typename T>
-__device__ __forceinline__ void stage_stencil_inverse_rows(T* sc, const T* __restrict__ S,
-                                                           const T* __restrict__ Dinv, int k) {
-  T v[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
-    v[u] = e < 243 ? S[static_cast<size_t>(k) * 243 + e]
-                   : (e < 252 && Dinv ? Dinv[static_cast<size_t>(k) * 9 + e - 243] : T(0));
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = threadIdx.x + u * static_cast<int>(blockDim.x);
-    if (e < 243)
-      sc[(e / 27) * 28 + e % 27] = v[u];
-    else if (e < 252 && Dinv)
-      sc[9 * 28 + e - 243] = v[u];
-  }
-}
-
-// One padded row of 28 entries from LDS in 16-byte reads.
-template <typename T>
-__device__ __forceinline__ void lds_row28(const T* p, T out[28]) {
-  constexpr int per = 16 / static_cast<int>(sizeof(T));
-  typedef T Vn __attribute__((ext_vector_type(16 / sizeof(T))));
-#pragma unroll
-  for (int u = 0; u < 28 / per; ++u) {
-    const Vn v = *reinterpret_cast<const Vn*>(p + u * per);
-#pragma unroll
-    for (int i = 0; i < per; ++i) out[u * per + i] = v[i];
-  }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* __restrict__ b,
                                                     int nx, int ny, int nz, ColourRange cr,
                                                     const T* __restrict__ S,
                                                     const T* __restrict__ Dinv) {
-  // blockIdx.y selects the plane; its stencil is staged in LDS and read as
-  // broadcasts.  The three neighbour planes are visited in a loop that is not
+  // blockIdx.y selects the plane; its stencil S[k][oz][y][x][c][d] and
+  // inverse centre block are uniform over the workgroup and read with scalar
+  // loads.  The three neighbour planes are visited in a loop that is not
   // unrolled; each visit issues its 27 loads together (the centre node's are
   // unused), so a thread waits for three rounds of memory latency.
-  __shared__ T sc[252];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = t < cr.hx * cr.hy;
   const int tt = active ? t : 0;
   const int ii = tt % cr.hx;
   const int jj = tt / cr.hx;
   const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
-  stage_stencil_inverse<T>(sc, S, Dinv, k);
+  const T* __restrict__ Sk = S + static_cast<size_t>(k) * 243;
+  const T* __restrict__ Di = Dinv + static_cast<size_t>(k) * 9;
   const int i = 2 * ii + cr.a, j = 2 * jj + cr.bb;
   const int P = nx * ny, C = (nz + 1) * P;
   const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
@@ -179,7 +123,6 @@ __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* 
   T acc[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
-  __syncthreads();
   if (!active) return;
 #pragma unroll 1
   for (int oz = 0; oz < 3; ++oz) {
@@ -194,13 +137,12 @@ __global__ __launch_bounds__(256) void k_colour_gen(T* __restrict__ x, const T* 
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       if (oz == 1 && q == 4) continue;  // centre block
-      const T* B = sc + (oz * 9 + q) * 9;
+      const T* B = Sk + (oz * 9 + q) * 9;
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         acc[c] -= B[c * 3] * nb[q][0] + B[c * 3 + 1] * nb[q][1] + B[c * 3 + 2] * nb[q][2];
     }
   }
-  const T* Di = sc + 243;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
     x[c * C + o] = Di[c * 3] * acc[0] + Di[c * 3 + 1] * acc[1] + Di[c * 3 + 2] * acc[2];
@@ -287,55 +229,74 @@ __global__ __launch_bounds__(kReduceBlock) void k_residual_fine(
   }
 }
 
+// r = b - A x on a coarse level, one node per thread.  blockIdx.y selects the
+// plane; its packed stencil (entries that vanish by symmetry left out, see
+// packed_stencil.h) is uniform over the workgroup and read with scalar loads.
+// All 81 neighbour loads are issued before the first is used.  ZERO_INT: x's
+// interior is taken as zero, so only the couplings into the wall planes
+// remain (a plane next to a wall).
 template <typename T, bool ZERO_INT>
 __global__ __launch_bounds__(kReduceBlock) void k_residual_gen(const T* __restrict__ x,
                                                                const T* __restrict__ b,
                                                                T* __restrict__ r, int nx, int ny,
-                                                               int nz, const T* __restrict__ S,
+                                                               int nz, const T* __restrict__ Pst,
                                                                double* __restrict__ partial) {
-  // blockIdx.y selects the plane; its stencil is staged in LDS.  The three
-  // neighbour planes are visited in a loop that is not unrolled: each visit
-  // issues its 27 loads together, so a thread waits for three rounds of memory
-  // latency and holds one plane's neighbours in registers.
-  __shared__ __align__(16) T sc[9 * 28];  // rows (oz, y) padded to 28
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 1 + static_cast<int>(blockIdx.y);
+  const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;
   const bool active = t < nx * ny;
-  stage_stencil_inverse_rows<T>(sc, S, nullptr, k);
   const int tt = active ? t : 0;
-  const int P = nx * ny, C = (nz + 1) * P;
+  const unsigned P = static_cast<unsigned>(nx * ny), C = static_cast<unsigned>(nz + 1) * P;
   const int i = tt % nx, j = tt / nx;
-  const int xs[3] = {wrap_m(i, nx), i, wrap_p(i, nx)};
-  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-  const int o = k * P + j * nx + i;
+  const unsigned xs[3] = {static_cast<unsigned>(wrap_m(i, nx)), static_cast<unsigned>(i),
+                          static_cast<unsigned>(wrap_p(i, nx))};
+  const unsigned ys[3] = {static_cast<unsigned>(wrap_m(j, ny)) * nx, static_cast<unsigned>(j) * nx,
+                          static_cast<unsigned>(wrap_p(j, ny)) * nx};
+  const unsigned o = k * P + j * nx + i;
   T acc[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) acc[c] = b[c * C + o];
-  __syncthreads();
+  // the three neighbour planes in a loop that is not unrolled, each visit
+  // issuing its 27 loads together and running the body of that plane (see
+  // k_colour_pair_gen)
 #pragma unroll 1
   for (int oz = 0; oz < 3; ++oz) {
     const int kk = k + oz - 1;
-    if (ZERO_INT && kk != 0 && kk != nz) continue;
+    if (ZERO_INT && kk != 0 && kk != nz) continue;  // interior plane, taken as zero
     T nb[9][3];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      const int off = kk * P + ys[q / 3] * nx + xs[q % 3];
+      const unsigned off = kk * P + ys[q / 3] + xs[q % 3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) nb[q][c] = x[c * C + off];
     }
+    auto apply = [&](auto OZ) {
+      constexpr int ozc = decltype(OZ)::value;
+      int n = packed_plane_start(ozc);
 #pragma unroll
-    for (int y = 0; y < 3; ++y) {
-      T cb[28];
-      lds_row28<T>(sc + (oz * 3 + y) * 28, cb);
+      for (int y = 0; y < 3; ++y)
 #pragma unroll
-      for (int x3 = 0; x3 < 3; ++x3) {
-        const int q = y * 3 + x3;
-        const T* B = cb + x3 * 9;
+        for (int q = 0; q < 3; ++q) {
+          if (ozc == 1 && y == 1 && q == 1) {  // centre block: diagonal
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          acc[c] -= B[c * 3] * nb[q][0] + B[c * 3 + 1] * nb[q][1] + B[c * 3 + 2] * nb[q][2];
-      }
-    }
+            for (int c = 0; c < 3; ++c) acc[c] = fma(-Pk[kPackedCentre + c], nb[4][c], acc[c]);
+            continue;
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              if (!packed_used(ozc, y, q, c, d)) continue;
+              acc[c] = fma(-Pk[n++], nb[y * 3 + q][d], acc[c]);
+            }
+        }
+    };
+    if (oz == 0)
+      apply(std::integral_constant<int, 0>());
+    else if (oz == 1)
+      apply(std::integral_constant<int, 1>());
+    else
+      apply(std::integral_constant<int, 2>());
   }
   double sq = 0.0;
   if (active) {
@@ -373,14 +334,17 @@ struct Pair<double> {
 // summed while the a-node is.  Neighbour values of both nodes are read as
 // pairs plus the two outer columns (four columns per row), so a launch moves
 // half the loads of two single-colour launches.
+//
+// A workgroup lies in one plane, so the plane's packed stencil (150 entries
+// and the inverse centre block) is the same for all its lanes: it is read
+// with scalar loads and enters the multiply-adds as a scalar operand.  All
+// neighbour loads of the three planes are issued before the first is used.
 template <typename T, int XF>
 __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, const T* __restrict__ b,
                                                          int nx, int ny, int nz, ColourRange cr,
                                                          int rows_per_block,
-                                                         const T* __restrict__ S,
-                                                         const T* __restrict__ Dinv) {
+                                                         const T* __restrict__ Pst) {
   using V = typename Pair<T>::type;
-  __shared__ __align__(16) T sc[9 * 28 + 9];  // 9 rows (oz, y) of 27 entries, padded; D^-1
   __shared__ T xa[3][256];
   const int W = nx / 2;  // column pairs per row
   const int tid = threadIdx.x;
@@ -388,15 +352,16 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
   const int jj = blockIdx.x * rows_per_block + rr;
   const bool active = rr < rows_per_block && jj < cr.hy;
   const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
-  stage_stencil_inverse_rows<T>(sc, S, Dinv, k);
+  const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
   constexpr int xf = XF;  // x parity of the colour updated first (cr.a)
   const int j = 2 * (active ? jj : 0) + cr.bb;
   const int i0 = 2 * p;
-  const int P = nx * ny, C = (nz + 1) * P;
-  const int il = i0 == 0 ? nx - 1 : i0 - 1;       // column i0-1
-  const int ir = i0 + 2 == nx ? 0 : i0 + 2;       // column i0+2
-  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-  const int o = k * P + j * nx + i0;
+  const unsigned P = static_cast<unsigned>(nx * ny), C = static_cast<unsigned>(nz + 1) * P;
+  const unsigned il = i0 == 0 ? nx - 1 : i0 - 1;  // column i0-1
+  const unsigned ir = i0 + 2 == nx ? 0 : i0 + 2;  // column i0+2
+  const unsigned ys[3] = {static_cast<unsigned>(wrap_m(j, ny)), static_cast<unsigned>(j),
+                          static_cast<unsigned>(wrap_p(j, ny))};
+  const unsigned o = k * P + j * nx + i0;
   T acca[3], accb[3];
   {
     V bv[3];
@@ -408,53 +373,59 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
       accb[c] = xf ? bv[c].x : bv[c].y;
     }
   }
-  __syncthreads();
-  // columns of the four-wide window: w[0] = i0-1, w[1] = i0, w[2] = i0+1,
-  // w[3] = i0+2; the node at column i0 + s uses w[s .. s+2]
+  // columns of the four-wide window: w[.][0] = i0-1, [1] = i0, [2] = i0+1,
+  // [3] = i0+2; the node at column i0 + s uses columns s .. s+2
   constexpr int sa = xf, sb = 1 - xf;
-  T side[2][3];  // b-node's x neighbours in its own row and plane, summed last
+  // The three neighbour planes are visited in a loop that is not unrolled;
+  // each visit issues its 36 loads together and runs the body of that plane
+  // (the planes differ in which stencil entries are packed), with the running
+  // index into the packed stencil a constant in each body.  The b-node's x
+  // neighbours in its own row and plane (blocks (1,1,0) and (1,1,2)) are
+  // applied after the exchange.
 #pragma unroll 1
   for (int oz = 0; oz < 3; ++oz) {
-    const int kk = k + oz - 1;
+    const unsigned kk = k + oz - 1;
     T w[3][4][3];
 #pragma unroll
     for (int y = 0; y < 3; ++y) {
-      const int row = kk * P + ys[y] * nx;
+      const unsigned row = kk * P + ys[y] * nx;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const V v = *reinterpret_cast<const V*>(x + c * C + row + i0);
+        const V v = *reinterpret_cast<const V*>(x + (c * C + row + i0));
         w[y][1][c] = v.x;
         w[y][2][c] = v.y;
         w[y][0][c] = x[c * C + row + il];
         w[y][3][c] = x[c * C + row + ir];
       }
     }
+    auto apply = [&](auto OZ) {
+      constexpr int ozc = decltype(OZ)::value;
+      int n = packed_plane_start(ozc);
 #pragma unroll
-    for (int y = 0; y < 3; ++y) {
-      // the row's three blocks (27 entries, padded to 28) come from LDS in
-      // 16-byte reads issued together, so a thread waits for LDS about once
-      // per row (small levels run one wavefront per SIMD, which hides nothing)
-      T cb[28];
-      lds_row28<T>(sc + (oz * 3 + y) * 28, cb);
+      for (int y = 0; y < 3; ++y)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const T* B = cb + q * 9;
-        if (oz == 1 && y == 1) {
-          if (q == 1) continue;  // centre blocks
-        } else {
+        for (int q = 0; q < 3; ++q) {
+          if (ozc == 1 && y == 1 && q == 1) continue;  // centre block
+          const bool later = ozc == 1 && y == 1;
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            accb[c] -= B[c * 3] * w[y][q + sb][0] + B[c * 3 + 1] * w[y][q + sb][1] +
-                       B[c * 3 + 2] * w[y][q + sb][2];
-        }
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-          acca[c] -= B[c * 3] * w[y][q + sa][0] + B[c * 3 + 1] * w[y][q + sa][1] +
-                     B[c * 3 + 2] * w[y][q + sa][2];
-      }
-    }
+            for (int d = 0; d < 3; ++d) {
+              if (!packed_used(ozc, y, q, c, d)) continue;
+              const T co = Pk[n++];
+              acca[c] = fma(-co, w[y][q + sa][d], acca[c]);
+              if (!later) accb[c] = fma(-co, w[y][q + sb][d], accb[c]);
+            }
+        }
+    };
+    if (oz == 0)
+      apply(std::integral_constant<int, 0>());
+    else if (oz == 1)
+      apply(std::integral_constant<int, 1>());
+    else
+      apply(std::integral_constant<int, 2>());
   }
-  const T* Di = sc + 9 * 28;
+  const T* Di = Pk + kPackedInv;
   T na[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) na[c] = Di[c * 3] * acca[0] + Di[c * 3 + 1] * acca[1] + Di[c * 3 + 2] * acca[2];
@@ -465,18 +436,22 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
   // the side away from it
   const int pn = xf ? (p == 0 ? W - 1 : p - 1) : (p == W - 1 ? 0 : p + 1);
   const int tn = active ? rr * W + pn : tid;
+  T side[2][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     side[xf][c] = na[c];       // xf = 0: left neighbour (i0) is own; xf = 1: right (i0+1)
     side[1 - xf][c] = xa[c][tn];
   }
-  {
-    const T* Bl = sc + (3 + 1) * 28 + 0 * 9;  // oz = 1, y = 1, q = 0: x - 1
-    const T* Br = sc + (3 + 1) * 28 + 2 * 9;  // q = 2: x + 1
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) {
+    int m = packed_block_start(1, 1, 2 * s2);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-      accb[c] -= Bl[c * 3] * side[0][0] + Bl[c * 3 + 1] * side[0][1] + Bl[c * 3 + 2] * side[0][2] +
-                 (Br[c * 3] * side[1][0] + Br[c * 3 + 1] * side[1][1] + Br[c * 3 + 2] * side[1][2]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (!packed_used(1, 1, 2 * s2, c, d)) continue;
+        accb[c] = fma(-Pk[m++], side[s2][d], accb[c]);
+      }
   }
   if (!active) return;
 #pragma unroll
@@ -498,22 +473,22 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__ x,
                                                            const T* __restrict__ b,
                                                            T* __restrict__ r, int nx, int ny,
-                                                           int nz, const T* __restrict__ S) {
+                                                           int nz, const T* __restrict__ Pst) {
   using V = typename Pair<T>::type;
-  __shared__ __align__(16) T sc[9 * 28];  // rows (oz, y) padded to 28
   const int W = nx / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = 1 + static_cast<int>(blockIdx.y);
+  const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
   const bool active = t < W * ny;
-  stage_stencil_inverse_rows<T>(sc, S, nullptr, k);
   const int tt = active ? t : 0;
   const int p = tt % W, j = tt / W;
   const int i0 = 2 * p;
-  const int P = nx * ny, C = (nz + 1) * P;
-  const int il = i0 == 0 ? nx - 1 : i0 - 1;  // column i0-1
-  const int ir = i0 + 2 == nx ? 0 : i0 + 2;  // column i0+2
-  const int ys[3] = {wrap_m(j, ny), j, wrap_p(j, ny)};
-  const int o = k * P + j * nx + i0;
+  const unsigned P = static_cast<unsigned>(nx * ny), C = static_cast<unsigned>(nz + 1) * P;
+  const unsigned il = i0 == 0 ? nx - 1 : i0 - 1;  // column i0-1
+  const unsigned ir = i0 + 2 == nx ? 0 : i0 + 2;  // column i0+2
+  const unsigned ys[3] = {static_cast<unsigned>(wrap_m(j, ny)), static_cast<unsigned>(j),
+                          static_cast<unsigned>(wrap_p(j, ny))};
+  const unsigned o = k * P + j * nx + i0;
   T acc0[3], acc1[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -521,38 +496,55 @@ __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__
     acc0[c] = bv.x;
     acc1[c] = bv.y;
   }
-  __syncthreads();
 #pragma unroll 1
   for (int oz = 0; oz < 3; ++oz) {
-    const int kk = k + oz - 1;
+    const unsigned kk = k + oz - 1;
     T w[3][4][3];  // rows j-1, j, j+1; columns i0-1 .. i0+2
 #pragma unroll
     for (int y = 0; y < 3; ++y) {
-      const int row = kk * P + ys[y] * nx;
+      const unsigned row = kk * P + ys[y] * nx;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const V v = *reinterpret_cast<const V*>(x + c * C + row + i0);
+        const V v = *reinterpret_cast<const V*>(x + (c * C + row + i0));
         w[y][1][c] = v.x;
         w[y][2][c] = v.y;
         w[y][0][c] = x[c * C + row + il];
         w[y][3][c] = x[c * C + row + ir];
       }
     }
+    // the planes differ in which entries are packed: one body per plane
+    auto apply = [&](auto OZ) {
+      constexpr int ozc = decltype(OZ)::value;
+      int n = packed_plane_start(ozc);
 #pragma unroll
-    for (int y = 0; y < 3; ++y) {
-      T cb[28];
-      lds_row28<T>(sc + (oz * 3 + y) * 28, cb);
+      for (int y = 0; y < 3; ++y)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const T* B = cb + q * 9;
+        for (int q = 0; q < 3; ++q) {
+          if (ozc == 1 && y == 1 && q == 1) {  // centre block: diagonal
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          acc0[c] -= B[c * 3] * w[y][q][0] + B[c * 3 + 1] * w[y][q][1] + B[c * 3 + 2] * w[y][q][2];
-          acc1[c] -= B[c * 3] * w[y][q + 1][0] + B[c * 3 + 1] * w[y][q + 1][1] +
-                     B[c * 3 + 2] * w[y][q + 1][2];
+            for (int c = 0; c < 3; ++c) {
+              acc0[c] = fma(-Pk[kPackedCentre + c], w[1][1][c], acc0[c]);
+              acc1[c] = fma(-Pk[kPackedCentre + c], w[1][2][c], acc1[c]);
+            }
+            continue;
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              if (!packed_used(ozc, y, q, c, d)) continue;
+              const T co = Pk[n++];
+              acc0[c] = fma(-co, w[y][q][d], acc0[c]);
+              acc1[c] = fma(-co, w[y][q + 1][d], acc1[c]);
+            }
         }
-      }
-    }
+    };
+    if (oz == 0)
+      apply(std::integral_constant<int, 0>());
+    else if (oz == 1)
+      apply(std::integral_constant<int, 1>());
+    else
+      apply(std::integral_constant<int, 2>());
   }
   if (!active) return;
 #pragma unroll
@@ -719,49 +711,40 @@ __global__ void k_fill(T* __restrict__ x, size_t n, T v) {
   for (; t < n; t += stride) x[t] = v;
 }
 
+// The coarsest solve in one launch: x_interior = A^-1 b_interior with the
+// interior unknowns in the order (component, plane, row, column); each lane
+// reads its b entries straight from the node vector (in double) and the row's
+// result goes straight to x, so no gathered copy of b is made.
 template <typename T>
-__global__ void k_gather(const T* __restrict__ b, double* __restrict__ out, int nx, int ny, int nz) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int P = nx * ny, per = P * (nz - 1);
-  if (t >= 3 * per) return;
-  const int c = t / per, rem = t - c * per;
-  out[t] = static_cast<double>(b[static_cast<size_t>(c) * (nz + 1) * P + P + rem]);
-}
-
-template <typename T>
-__global__ void k_scatter(const double* __restrict__ in, T* __restrict__ x, int nx, int ny, int nz) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int P = nx * ny, per = P * (nz - 1);
-  if (t >= 3 * per) return;
-  const int c = t / per, rem = t - c * per;
-  x[static_cast<size_t>(c) * (nz + 1) * P + P + rem] = static_cast<T>(in[t]);
-}
-
-// One 64-lane wavefront per row of the dense coarsest inverse.
-__global__ __launch_bounds__(256) void k_dense_matvec(const double* __restrict__ A,
-                                                      const double* __restrict__ v,
-                                                      double* __restrict__ out, int n) {
+__global__ __launch_bounds__(256) void k_coarse_apply(const double* __restrict__ A,
+                                                      const T* __restrict__ b, T* __restrict__ x,
+                                                      int n, int P, int nz) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
+  const int per = P * (nz - 1);              // interior unknowns per component
+  const size_t C = static_cast<size_t>(nz + 1) * P;
+  auto at = [&](int q) -> size_t {            // node-vector index of unknown q
+    const int c = (q >= per) + (q >= 2 * per);
+    return c * C + P + (q - c * per);
+  };
   const double* a = A + static_cast<size_t>(row) * n;
-  // four independent partial sums, so that each step issues eight loads
-  // before it waits
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int q = lane;
   for (; q + 192 < n; q += 256) {
     const double a0 = a[q], a1 = a[q + 64], a2 = a[q + 128], a3 = a[q + 192];
-    const double v0 = v[q], v1 = v[q + 64], v2 = v[q + 128], v3 = v[q + 192];
+    const double v0 = static_cast<double>(b[at(q)]), v1 = static_cast<double>(b[at(q + 64)]);
+    const double v2 = static_cast<double>(b[at(q + 128)]), v3 = static_cast<double>(b[at(q + 192)]);
     s0 += a0 * v0;
     s1 += a1 * v1;
     s2 += a2 * v2;
     s3 += a3 * v3;
   }
-  for (; q < n; q += 64) s0 += a[q] * v[q];
+  for (; q < n; q += 64) s0 += a[q] * static_cast<double>(b[at(q)]);
   double s = (s0 + s1) + (s2 + s3);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) out[row] = s;
+  if (lane == 0) x[at(row)] = static_cast<T>(s);
 }
 
 inline int blocks_for(long long n, int bs) { return static_cast<int>((n + bs - 1) / bs); }
@@ -788,8 +771,7 @@ void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T
 bool colour_pair_supported(Dims d) { return d.nx % 2 == 0 && d.nx >= 2 && d.nx <= 512; }
 
 template <typename T>
-void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, const T* Dinv,
-                            hipStream_t s) {
+void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* Pst, hipStream_t s) {
   // colour is the one updated first; its partner is colour ^ 1
   const ColourRange cr = colour_range(d, colour);
   if (cr.total() <= 0) return;
@@ -801,17 +783,17 @@ void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* S, co
   const dim3 grid(blocks_for(cr.hy, rpb), cr.nk);
   if (cr.a)
     hipLaunchKernelGGL((k_colour_pair_gen<T, 1>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
-                       cr, rpb, S, Dinv);
+                       cr, rpb, Pst);
   else
     hipLaunchKernelGGL((k_colour_pair_gen<T, 0>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
-                       cr, rpb, S, Dinv);
+                       cr, rpb, Pst);
 }
 
 template <typename T>
-void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* S, hipStream_t s) {
+void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* Pst, hipStream_t s) {
   const dim3 grid(blocks_for(static_cast<long long>(d.nx / 2) * d.ny, 256), d.nz - 1);
   if (d.nz - 1 <= 0) return;
-  hipLaunchKernelGGL(k_residual_pair_gen<T>, grid, dim3(256), 0, s, x, b, r, d.nx, d.ny, d.nz, S);
+  hipLaunchKernelGGL(k_residual_pair_gen<T>, grid, dim3(256), 0, s, x, b, r, d.nx, d.ny, d.nz, Pst);
 }
 
 int residual_blocks(Dims d) {
@@ -842,15 +824,15 @@ int launch_residual_fine(const Tin* x, const Tin* b, Tout* r, Dims d, const Fine
 }
 
 template <typename T>
-int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* S, bool zero_interior,
+int launch_residual_gen(const T* x, const T* b, T* r, Dims d, const T* Pst, bool zero_interior,
                         double* partial, hipStream_t s) {
   const dim3 grid(blocks_for(static_cast<long long>(d.nx) * d.ny, kReduceBlock), d.nz - 1);
   if (zero_interior)
     hipLaunchKernelGGL((k_residual_gen<T, true>), grid, dim3(kReduceBlock), 0, s, x, b, r, d.nx,
-                       d.ny, d.nz, S, partial);
+                       d.ny, d.nz, Pst, partial);
   else
-    hipLaunchKernelGGL((k_residual_gen<T, false>), grid, dim3(kReduceBlock), 0, s, x, b, r,
-                       d.nx, d.ny, d.nz, S, partial);
+    hipLaunchKernelGGL((k_residual_gen<T, false>), grid, dim3(kReduceBlock), 0, s, x, b, r, d.nx,
+                       d.ny, d.nz, Pst, partial);
   return static_cast<int>(grid.x * grid.y);
 }
 
@@ -899,19 +881,16 @@ void launch_zero_interior(T* x, Dims d, hipStream_t s) {
 }
 
 template <typename T>
-void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, double* tin,
-                         double* tout, hipStream_t s) {
-  const int nb = blocks_for(n, 256);
-  hipLaunchKernelGGL(k_gather<T>, dim3(nb), dim3(256), 0, s, b, tin, d.nx, d.ny, d.nz);
-  hipLaunchKernelGGL(k_dense_matvec, dim3(blocks_for(n, 4)), dim3(256), 0, s, Ainv, tin, tout, n);
-  hipLaunchKernelGGL(k_scatter<T>, dim3(nb), dim3(256), 0, s, tout, x, d.nx, d.ny, d.nz);
+void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_coarse_apply<T>, dim3(blocks_for(n, 4)), dim3(256), 0, s, Ainv, b, x, n,
+                     d.plane(), d.nz);
 }
 
 #define QS_INST(T)                                                                               \
   template void launch_colour_fine<T>(T*, const T*, Dims, int, const FineCoef<T>&, hipStream_t); \
   template void launch_colour_gen<T>(T*, const T*, Dims, int, const T*, const T*, hipStream_t);  \
-  template void launch_colour_pair_gen<T>(T*, const T*, Dims, int, const T*, const T*,           \
-                                          hipStream_t);                                          \
+  template void launch_colour_pair_gen<T>(T*, const T*, Dims, int, const T*, hipStream_t);       \
   template void launch_residual_pair_gen<T>(const T*, const T*, T*, Dims, const T*, hipStream_t); \
   template int launch_residual_gen<T>(const T*, const T*, T*, Dims, const T*, bool, double*,     \
                                       hipStream_t);                                              \
@@ -919,8 +898,7 @@ void launch_coarse_solve(const double* Ainv, int n, const T* b, T* x, Dims d, do
   template void launch_prolong_add<T>(T*, const T*, Dims, hipStream_t);                          \
   template void launch_fill<T>(T*, size_t, T, hipStream_t);                                      \
   template void launch_zero_interior<T>(T*, Dims, hipStream_t);                                  \
-  template void launch_coarse_solve<T>(const double*, int, const T*, T*, Dims, double*, double*, \
-                                       hipStream_t);
+  template void launch_coarse_solve<T>(const double*, int, const T*, T*, Dims, hipStream_t);
 QS_INST(double)
 QS_INST(float)
 #undef QS_INST
