@@ -337,110 +337,118 @@ struct Pair<double> {
 //
 // A workgroup lies in one plane, so the plane's packed stencil (150 entries
 // and the inverse centre block) is the same for all its lanes: it is read
-// with scalar loads and enters the multiply-adds as a scalar operand.  All
-// neighbour loads of the three planes are issued before the first is used.
-template <typename T, int XF>
-__global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, const T* __restrict__ b,
-                                                         int nx, int ny, int nz, ColourRange cr,
-                                                         int rows_per_block,
-                                                         const T* __restrict__ Pst) {
+// with scalar loads and enters the multiply-adds as a scalar operand.  The
+// three neighbour planes differ in which entries are packed, so each has a
+// body of its own in which the running index into the packed stencil is a
+// constant; a body is entered through a branch on the plane, so that the
+// scalar loads of one plane are not scheduled with those of the others.
+
+// Where a thread's column pair and rows lie.
+template <typename T>
+struct PairSite {
+  int W, rr, p, j, i0;
+  bool active;
+  unsigned P, C, il, ir, o;
+  unsigned ys[3];
+  __device__ PairSite(int tid, int nx, int ny, int nz, const ColourRange& cr, int rows_per_block,
+                      int k) {
+    W = nx / 2;  // column pairs per row
+    rr = tid / W;
+    p = tid - rr * W;
+    const int jj = static_cast<int>(blockIdx.x) * rows_per_block + rr;
+    active = rr < rows_per_block && jj < cr.hy;
+    j = 2 * (active ? jj : 0) + cr.bb;
+    i0 = 2 * p;
+    P = static_cast<unsigned>(nx * ny);
+    C = static_cast<unsigned>(nz + 1) * P;
+    il = i0 == 0 ? nx - 1 : i0 - 1;  // column i0-1
+    ir = i0 + 2 == nx ? 0 : i0 + 2;  // column i0+2
+    ys[0] = static_cast<unsigned>(wrap_m(j, ny)) * nx;
+    ys[1] = static_cast<unsigned>(j) * nx;
+    ys[2] = static_cast<unsigned>(wrap_p(j, ny)) * nx;
+    o = k * P + j * nx + i0;
+  }
+};
+
+// The four-wide window of the rows j-1, j, j+1 of plane kk: w[y][0] = column
+// i0-1, [1] = i0, [2] = i0+1, [3] = i0+2; the node at column i0 + s uses
+// columns s .. s+2.
+template <typename T>
+__device__ __forceinline__ void pair_window(const T* __restrict__ x, const PairSite<T>& st,
+                                            unsigned kk, T w[3][4][3]) {
   using V = typename Pair<T>::type;
-  __shared__ T xa[3][256];
-  const int W = nx / 2;  // column pairs per row
-  const int tid = threadIdx.x;
-  const int rr = tid / W, p = tid - rr * W;
-  const int jj = blockIdx.x * rows_per_block + rr;
-  const bool active = rr < rows_per_block && jj < cr.hy;
-  const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
-  const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
-  constexpr int xf = XF;  // x parity of the colour updated first (cr.a)
-  const int j = 2 * (active ? jj : 0) + cr.bb;
-  const int i0 = 2 * p;
-  const unsigned P = static_cast<unsigned>(nx * ny), C = static_cast<unsigned>(nz + 1) * P;
-  const unsigned il = i0 == 0 ? nx - 1 : i0 - 1;  // column i0-1
-  const unsigned ir = i0 + 2 == nx ? 0 : i0 + 2;  // column i0+2
-  const unsigned ys[3] = {static_cast<unsigned>(wrap_m(j, ny)), static_cast<unsigned>(j),
-                          static_cast<unsigned>(wrap_p(j, ny))};
-  const unsigned o = k * P + j * nx + i0;
-  T acca[3], accb[3];
-  {
-    V bv[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) bv[c] = *reinterpret_cast<const V*>(b + c * C + o);
+  for (int y = 0; y < 3; ++y) {
+    const unsigned row = kk * st.P + st.ys[y];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      acca[c] = xf ? bv[c].y : bv[c].x;
-      accb[c] = xf ? bv[c].x : bv[c].y;
+      const V v = *reinterpret_cast<const V*>(x + (c * st.C + row + st.i0));
+      w[y][1][c] = v.x;
+      w[y][2][c] = v.y;
+      w[y][0][c] = x[c * st.C + row + st.il];
+      w[y][3][c] = x[c * st.C + row + st.ir];
     }
   }
-  // columns of the four-wide window: w[.][0] = i0-1, [1] = i0, [2] = i0+1,
-  // [3] = i0+2; the node at column i0 + s uses columns s .. s+2
-  constexpr int sa = xf, sb = 1 - xf;
-  // The three neighbour planes are visited in a loop that is not unrolled;
-  // each visit issues its 36 loads together and runs the body of that plane
-  // (the planes differ in which stencil entries are packed), with the running
-  // index into the packed stencil a constant in each body.  The b-node's x
-  // neighbours in its own row and plane (blocks (1,1,0) and (1,1,2)) are
-  // applied after the exchange.
-#pragma unroll 1
-  for (int oz = 0; oz < 3; ++oz) {
-    const unsigned kk = k + oz - 1;
-    T w[3][4][3];
+}
+
+// Terms of neighbour plane OZ (0, 1, 2 for k-1, k, k+1) subtracted from the
+// a-node sum and the b-node sum; the b-node's blocks (1,1,0) and (1,1,2) wait
+// for the new a values (pair_side), the centre block is the inverse's.
+template <typename T, int OZ, int SA, int SB>
+__device__ __forceinline__ void pair_plane(const T* __restrict__ Pk, const T w[3][4][3],
+                                           T acca[3], T accb[3]) {
+  int n = packed_plane_start(OZ);
 #pragma unroll
-    for (int y = 0; y < 3; ++y) {
-      const unsigned row = kk * P + ys[y] * nx;
+  for (int y = 0; y < 3; ++y)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const V v = *reinterpret_cast<const V*>(x + (c * C + row + i0));
-        w[y][1][c] = v.x;
-        w[y][2][c] = v.y;
-        w[y][0][c] = x[c * C + row + il];
-        w[y][3][c] = x[c * C + row + ir];
-      }
-    }
-    auto apply = [&](auto OZ) {
-      constexpr int ozc = decltype(OZ)::value;
-      int n = packed_plane_start(ozc);
+    for (int q = 0; q < 3; ++q) {
+      if (OZ == 1 && y == 1 && q == 1) continue;  // centre block
+      const bool later = OZ == 1 && y == 1;
 #pragma unroll
-      for (int y = 0; y < 3; ++y)
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          if (ozc == 1 && y == 1 && q == 1) continue;  // centre block
-          const bool later = ozc == 1 && y == 1;
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              if (!packed_used(ozc, y, q, c, d)) continue;
-              const T co = Pk[n++];
-              acca[c] = fma(-co, w[y][q + sa][d], acca[c]);
-              if (!later) accb[c] = fma(-co, w[y][q + sb][d], accb[c]);
-            }
+        for (int d = 0; d < 3; ++d) {
+          if (!packed_used(OZ, y, q, c, d)) continue;
+          const T co = Pk[n++];
+          acca[c] = fma(-co, w[y][q + SA][d], acca[c]);
+          if (!later) accb[c] = fma(-co, w[y][q + SB][d], accb[c]);
         }
-    };
-    if (oz == 0)
-      apply(std::integral_constant<int, 0>());
-    else if (oz == 1)
-      apply(std::integral_constant<int, 1>());
-    else
-      apply(std::integral_constant<int, 2>());
-  }
-  const T* Di = Pk + kPackedInv;
-  T na[3];
+    }
+}
+
+template <typename T, int SA, int SB>
+__device__ __forceinline__ void pair_plane_rt(int oz, const T* __restrict__ Pk, const T w[3][4][3],
+                                              T acca[3], T accb[3]) {
+  if (oz == 0)
+    pair_plane<T, 0, SA, SB>(Pk, w, acca, accb);
+  else if (oz == 1)
+    pair_plane<T, 1, SA, SB>(Pk, w, acca, accb);
+  else
+    pair_plane<T, 2, SA, SB>(Pk, w, acca, accb);
+}
+
+// D^-1 times a sum
+template <typename T>
+__device__ __forceinline__ void apply_inv(const T* __restrict__ Di, const T acc[3], T out[3]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) na[c] = Di[c * 3] * acca[0] + Di[c * 3 + 1] * acca[1] + Di[c * 3 + 2] * acca[2];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
-  __syncthreads();
-  // the b-node's x neighbours of colour a: own a-node and that of the pair on
-  // the side away from it
-  const int pn = xf ? (p == 0 ? W - 1 : p - 1) : (p == W - 1 ? 0 : p + 1);
-  const int tn = active ? rr * W + pn : tid;
+  for (int c = 0; c < 3; ++c) out[c] = Di[c * 3] * acc[0] + Di[c * 3 + 1] * acc[1] + Di[c * 3 + 2] * acc[2];
+}
+
+// The b-node's x neighbours of colour a (the own a-node na and, from LDS xa,
+// that of the pair on the side away from it), its last terms, its new value,
+// and the store of the pair.
+template <typename T, int XF>
+__device__ __forceinline__ void pair_finish(T* __restrict__ x, const PairSite<T>& st,
+                                            const T* __restrict__ Pk, const T (*xa)[256], int tid,
+                                            const T na[3], T accb[3]) {
+  using V = typename Pair<T>::type;
+  const int pn = XF ? (st.p == 0 ? st.W - 1 : st.p - 1) : (st.p == st.W - 1 ? 0 : st.p + 1);
+  const int tn = st.active ? st.rr * st.W + pn : tid;
   T side[2][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    side[xf][c] = na[c];       // xf = 0: left neighbour (i0) is own; xf = 1: right (i0+1)
-    side[1 - xf][c] = xa[c][tn];
+    side[XF][c] = na[c];  // XF = 0: left neighbour (i0) is own; XF = 1: right (i0+1)
+    side[1 - XF][c] = xa[c][tn];
   }
 #pragma unroll
   for (int s2 = 0; s2 < 2; ++s2) {
@@ -453,15 +461,108 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
         accb[c] = fma(-Pk[m++], side[s2][d], accb[c]);
       }
   }
-  if (!active) return;
+  if (!st.active) return;
+  T nb[3];
+  apply_inv<T>(Pk + kPackedInv, accb, nb);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const T nb = Di[c * 3] * accb[0] + Di[c * 3 + 1] * accb[1] + Di[c * 3 + 2] * accb[2];
     V v;
-    v.x = xf ? nb : na[c];
-    v.y = xf ? na[c] : nb;
-    *reinterpret_cast<V*>(x + c * C + o) = v;
+    v.x = XF ? nb[c] : na[c];
+    v.y = XF ? na[c] : nb[c];
+    *reinterpret_cast<V*>(x + c * st.C + st.o) = v;
   }
+}
+
+// One thread per column pair: the three neighbour planes in a loop that is
+// not unrolled, each visit issuing its 36 loads together (128^3 and larger).
+template <typename T, int XF>
+__global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, const T* __restrict__ b,
+                                                         int nx, int ny, int nz, ColourRange cr,
+                                                         int rows_per_block,
+                                                         const T* __restrict__ Pst) {
+  using V = typename Pair<T>::type;
+  __shared__ T xa[3][256];
+  const int tid = threadIdx.x;
+  const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
+  const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
+  const PairSite<T> st(tid, nx, ny, nz, cr, rows_per_block, k);
+  T acca[3], accb[3];
+  {
+    V bv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bv[c] = *reinterpret_cast<const V*>(b + c * st.C + st.o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      acca[c] = XF ? bv[c].y : bv[c].x;
+      accb[c] = XF ? bv[c].x : bv[c].y;
+    }
+  }
+#pragma unroll 1
+  for (int oz = 0; oz < 3; ++oz) {
+    T w[3][4][3];
+    pair_window<T>(x, st, k + oz - 1, w);
+    pair_plane_rt<T, XF, 1 - XF>(oz, Pk, w, acca, accb);
+  }
+  T na[3];
+  apply_inv<T>(Pk + kPackedInv, acca, na);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
+  __syncthreads();
+  pair_finish<T, XF>(x, st, Pk, xa, tid, na, accb);
+}
+
+// The same two colours with three threads per column pair, one per
+// neighbour plane (threadIdx.y), on the small levels (64^3 and below), where
+// a launch is a few waves and each round of memory latency shows: every
+// neighbour load of the pair is issued at once, across the three threads.
+// The partial sums of planes k-1 and k+1 meet the middle thread's in LDS;
+// the middle thread finishes the pair as above.
+template <typename T, int XF>
+__global__ __launch_bounds__(384) void k_colour_pair_split(T* __restrict__ x,
+                                                           const T* __restrict__ b, int nx,
+                                                           int ny, int nz, ColourRange cr,
+                                                           int rows_per_block,
+                                                           const T* __restrict__ Pst) {
+  using V = typename Pair<T>::type;
+  __shared__ T xa[3][256];
+  __shared__ T part[2][2][3][128];  // [plane k-1, k+1][a, b][component][pair]
+  const int tid = threadIdx.x, oz = threadIdx.y;
+  const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
+  const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
+  const PairSite<T> st(tid, nx, ny, nz, cr, rows_per_block, k);
+  T acca[3] = {T(0), T(0), T(0)}, accb[3] = {T(0), T(0), T(0)};
+  V bv[3];
+  if (oz == 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bv[c] = *reinterpret_cast<const V*>(b + c * st.C + st.o);
+  }
+  {
+    T w[3][4][3];
+    pair_window<T>(x, st, k + oz - 1, w);
+    pair_plane_rt<T, XF, 1 - XF>(oz, Pk, w, acca, accb);
+  }
+  if (oz != 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      part[oz >> 1][0][c][tid] = acca[c];
+      part[oz >> 1][1][c][tid] = accb[c];
+    }
+  }
+  __syncthreads();
+  T na[3];
+  if (oz == 1) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const T ba = XF ? bv[c].y : bv[c].x, bb = XF ? bv[c].x : bv[c].y;
+      acca[c] = ba + part[0][0][c][tid] + acca[c] + part[1][0][c][tid];
+      accb[c] = bb + part[0][1][c][tid] + accb[c] + part[1][1][c][tid];
+    }
+    apply_inv<T>(Pk + kPackedInv, acca, na);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
+  }
+  __syncthreads();
+  if (oz == 1) pair_finish<T, XF>(x, st, Pk, xa, tid, na, accb);
 }
 
 // Coarse residual r = b - A x (V-cycle form: no norm) for the column pair
@@ -776,11 +877,22 @@ void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* Pst, 
   const ColourRange cr = colour_range(d, colour);
   if (cr.total() <= 0) return;
   const int W = d.nx / 2;
-  // whole rows in workgroups of about 128 threads: more, smaller workgroups
-  // than 256-thread ones (measured: 5.3 against 6.3 us at 64^3, same at 128^3)
+  // whole rows in workgroups of about 128 column pairs: more, smaller
+  // workgroups than 256-pair ones (measured: 5.3 against 6.3 us at 64^3, same
+  // at 128^3)
   const int rpb = std::max(1, std::min(cr.hy, 128 / W));
-  const int threads = (rpb * W + 63) / 64 * 64;
   const dim3 grid(blocks_for(cr.hy, rpb), cr.nk);
+  if (d.nx <= 64) {  // small levels: three threads per pair
+    const dim3 block(rpb * W, 3);
+    if (cr.a)
+      hipLaunchKernelGGL((k_colour_pair_split<T, 1>), grid, block, 0, s, x, b, d.nx, d.ny, d.nz, cr,
+                         rpb, Pst);
+    else
+      hipLaunchKernelGGL((k_colour_pair_split<T, 0>), grid, block, 0, s, x, b, d.nx, d.ny, d.nz, cr,
+                         rpb, Pst);
+    return;
+  }
+  const int threads = (rpb * W + 63) / 64 * 64;
   if (cr.a)
     hipLaunchKernelGGL((k_colour_pair_gen<T, 1>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
                        cr, rpb, Pst);
