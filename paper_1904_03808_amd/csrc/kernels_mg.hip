@@ -350,12 +350,13 @@ struct PairSite {
   bool active;
   unsigned P, C, il, ir, o;
   unsigned ys[3];
+  // rb: the workgroup's block of rows_per_block rows of the colour
   __device__ PairSite(int tid, int nx, int ny, int nz, const ColourRange& cr, int rows_per_block,
-                      int k) {
+                      int rb, int k) {
     W = nx / 2;  // column pairs per row
     rr = tid / W;
     p = tid - rr * W;
-    const int jj = static_cast<int>(blockIdx.x) * rows_per_block + rr;
+    const int jj = rb * rows_per_block + rr;
     active = rr < rows_per_block && jj < cr.hy;
     j = 2 * (active ? jj : 0) + cr.bb;
     i0 = 2 * p;
@@ -475,17 +476,25 @@ __device__ __forceinline__ void pair_finish(T* __restrict__ x, const PairSite<T>
 
 // One thread per column pair: the three neighbour planes in a loop that is
 // not unrolled, each visit issuing its 36 loads together (128^3 and larger).
+// The grid is one-dimensional, gx row blocks times the colour's planes, in
+// an XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, and XCD
+// x takes the contiguous range [x per_xcd, (x+1) per_xcd) of (plane, row
+// block) pairs, so that the neighbour rows and planes a workgroup reads are
+// mostly fetched into the same L2 by the workgroups next to it.
 template <typename T, int XF>
 __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, const T* __restrict__ b,
                                                          int nx, int ny, int nz, ColourRange cr,
-                                                         int rows_per_block,
+                                                         int rows_per_block, int gx, int per_xcd,
                                                          const T* __restrict__ Pst) {
   using V = typename Pair<T>::type;
   __shared__ T xa[3][256];
+  const int wg = blockIdx.x;
+  const int L = (wg & 7) * per_xcd + (wg >> 3);
+  if (L >= gx * cr.nk) return;  // the whole workgroup, before any barrier
   const int tid = threadIdx.x;
-  const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
+  const int k = cr.kfirst + 2 * (L / gx);
   const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
-  const PairSite<T> st(tid, nx, ny, nz, cr, rows_per_block, k);
+  const PairSite<T> st(tid, nx, ny, nz, cr, rows_per_block, L % gx, k);
   T acca[3], accb[3];
   {
     V bv[3];
@@ -529,7 +538,7 @@ __global__ __launch_bounds__(384) void k_colour_pair_split(T* __restrict__ x,
   const int tid = threadIdx.x, oz = threadIdx.y;
   const int k = cr.kfirst + 2 * static_cast<int>(blockIdx.y);
   const T* __restrict__ Pk = Pst + static_cast<size_t>(k) * kPackedStencil;  // uniform
-  const PairSite<T> st(tid, nx, ny, nz, cr, rows_per_block, k);
+  const PairSite<T> st(tid, nx, ny, nz, cr, rows_per_block, blockIdx.x, k);
   T acca[3] = {T(0), T(0), T(0)}, accb[3] = {T(0), T(0), T(0)};
   V bv[3];
   if (oz == 1) {
@@ -893,12 +902,13 @@ void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* Pst, 
     return;
   }
   const int threads = (rpb * W + 63) / 64 * 64;
+  const int gx = static_cast<int>(grid.x), per_xcd = (gx * cr.nk + 7) / 8;
   if (cr.a)
-    hipLaunchKernelGGL((k_colour_pair_gen<T, 1>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
-                       cr, rpb, Pst);
+    hipLaunchKernelGGL((k_colour_pair_gen<T, 1>), dim3(8 * per_xcd), dim3(threads), 0, s, x, b, d.nx,
+                       d.ny, d.nz, cr, rpb, gx, per_xcd, Pst);
   else
-    hipLaunchKernelGGL((k_colour_pair_gen<T, 0>), grid, dim3(threads), 0, s, x, b, d.nx, d.ny, d.nz,
-                       cr, rpb, Pst);
+    hipLaunchKernelGGL((k_colour_pair_gen<T, 0>), dim3(8 * per_xcd), dim3(threads), 0, s, x, b, d.nx,
+                       d.ny, d.nz, cr, rpb, gx, per_xcd, Pst);
 }
 
 template <typename T>
