@@ -239,6 +239,36 @@ def test_row_sweep_matches_oracle(n, mc, prec):
             assert rel(host(xd).astype(np.float64), xr) < tol, (level, sweeps)
 
 
+def test_colour_passes_128_wide_level():
+    """256 x 256 x 32 on five levels (coarsest 16 x 16 x 2): level 1 is
+    128 x 128 x 16, the row width of the 128^3 level, smoothed by the
+    two-colour launch with one thread per column pair and the XCD-ordered
+    grid.  Colour passes match the oracle colour by colour, a whole sweep
+    matches, and so does a whole V-cycle from a random start."""
+    rng = np.random.default_rng(13)
+    n = (256, 256, 32)
+    g, o = make(*n, min_coarse_nz=2)
+    L = o.levels[1]
+    assert (L.nx, L.ny, L.nz) == (128, 128, 16) and g.levels == 5
+    x = rand_node(rng, L.nx, L.ny, L.nz, walls=False)
+    b = rand_node(rng, L.nx, L.ny, L.nz)
+    xd, bd = dev(x), dev(b)
+    for c in ROW:
+        g.level_colour_pass(1, xd, bd, c)
+        L.colour_pass(x, b, (c & 1, (c >> 1) & 1, (c >> 2) & 1))
+        assert rel(host(xd), x) < 1e-13, c
+    xd = dev(x)
+    g.smooth(1, xd, bd, 1)
+    L.sweep(x, b, o.order)
+    assert rel(host(xd), x) < 1e-13
+    bf = rand_node(rng, *n)
+    x0 = rand_node(rng, *n)
+    xd = dev(x0)
+    g.solve(dev(bf), xd, rtol=0.0, max_cycles=1)
+    x_ref, _ = o.solve(bf, x0, rtol=0.0, max_cycles=1)
+    assert rel(host(xd), x_ref) < 1e-12
+
+
 @pytest.mark.parametrize("n,mc", [((160, 24, 16), 4), ((64, 64, 64), 8)])
 @pytest.mark.parametrize("order", [ROW, (7, 6, 3, 2, 5, 4, 1, 0), (1, 0, 3, 2, 5, 4, 7, 6),
                                    (2, 3, 0, 1, 6, 7, 4, 5)])
