@@ -271,8 +271,12 @@ void residual(qs_handle* hd, int l, const T* x, const T* b, T* r, bool zero_inte
     launch_residual_fine_zm<T, T>(x, b, r, lb.d, hd->fc64, 1.0, nullptr, hd->stream);
   else if (l == 0)
     launch_residual_fine<T, T>(x, b, r, lb.d, hd->fc64, 1.0, zero_interior, nullptr, hd->stream);
-  else if (sizeof(T) == 8 && !zero_interior && lb.d.nx % 2 == 0 && aligned16(x) && aligned16(b) &&
-           aligned16(r))  // FP64: 56 against 88 us at 128^3; FP32 is faster one node per thread
+  else if ((sizeof(T) == 8 || pair_rows_in_lanes(lb.d)) && !zero_interior && lb.d.nx % 2 == 0 &&
+           aligned16(x) && aligned16(b) && aligned16(r))
+    // two nodes per thread; in FP32 only where a row's pairs fit the lanes of
+    // one wavefront and the outer window columns come by lane shuffles
+    // (128^3: 25 against 35 us for one node per thread, which stays faster
+    // when the outer columns are loaded)
     launch_residual_pair_gen<T>(x, b, r, lb.d, Prec<T>::Pk(lb), hd->stream);
   else
     launch_residual_gen<T>(x, b, r, lb.d, Prec<T>::Pk(lb), zero_interior, nullptr, hd->stream);

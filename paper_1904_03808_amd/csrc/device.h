@@ -62,6 +62,9 @@ void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T
 template <typename T>
 void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* Pst, hipStream_t s);
 bool colour_pair_supported(Dims d);
+// The column pairs of a row fill a power-of-two run of at most 64 lanes, so
+// the pair kernels take the outer window columns by lane shuffles.
+bool pair_rows_in_lanes(Dims d);
 // Coarse residual r = b - A x on the interior, two nodes per thread (even nx,
 // 16-byte aligned vectors), packed stencil.
 template <typename T>

@@ -373,23 +373,46 @@ struct PairSite {
 
 // The four-wide window of the rows j-1, j, j+1 of plane kk: w[y][0] = column
 // i0-1, [1] = i0, [2] = i0+1, [3] = i0+2; the node at column i0 + s uses
-// columns s .. s+2.
-template <typename T>
+// columns s .. s+2.  SHFL: the pairs of a row lie in W consecutive lanes of
+// one wavefront (W a power of two dividing 64), so the outer columns i0-1
+// and i0+2 are the neighbouring lanes' pair values (the periodic wrap is a
+// rotation within the row's lanes) and only the pairs are loaded: a third of
+// the load instructions.
+template <typename T, bool SHFL>
 __device__ __forceinline__ void pair_window(const T* __restrict__ x, const PairSite<T>& st,
                                             unsigned kk, T w[3][4][3]) {
   using V = typename Pair<T>::type;
+  V v[3][3];
 #pragma unroll
   for (int y = 0; y < 3; ++y) {
     const unsigned row = kk * st.P + st.ys[y];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const V v = *reinterpret_cast<const V*>(x + (c * st.C + row + st.i0));
-      w[y][1][c] = v.x;
-      w[y][2][c] = v.y;
-      w[y][0][c] = x[c * st.C + row + st.il];
-      w[y][3][c] = x[c * st.C + row + st.ir];
+      v[y][c] = *reinterpret_cast<const V*>(x + (c * st.C + row + st.i0));
+      if (!SHFL) {
+        w[y][0][c] = x[c * st.C + row + st.il];
+        w[y][3][c] = x[c * st.C + row + st.ir];
+      }
     }
   }
+  int lm = 0, lp = 0;  // lanes of the pairs p-1 and p+1 in the row
+  if (SHFL) {
+    const int lane = static_cast<int>(__lane_id());
+    const int base = lane & ~(st.W - 1);
+    lm = base + ((st.p + st.W - 1) & (st.W - 1));
+    lp = base + ((st.p + 1) & (st.W - 1));
+  }
+#pragma unroll
+  for (int y = 0; y < 3; ++y)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      w[y][1][c] = v[y][c].x;
+      w[y][2][c] = v[y][c].y;
+      if (SHFL) {
+        w[y][0][c] = __shfl(v[y][c].y, lm);
+        w[y][3][c] = __shfl(v[y][c].x, lp);
+      }
+    }
 }
 
 // Terms of neighbour plane OZ (0, 1, 2 for k-1, k, k+1) subtracted from the
@@ -481,7 +504,7 @@ __device__ __forceinline__ void pair_finish(T* __restrict__ x, const PairSite<T>
 // x takes the contiguous range [x per_xcd, (x+1) per_xcd) of (plane, row
 // block) pairs, so that the neighbour rows and planes a workgroup reads are
 // mostly fetched into the same L2 by the workgroups next to it.
-template <typename T, int XF>
+template <typename T, int XF, bool SHFL>
 __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, const T* __restrict__ b,
                                                          int nx, int ny, int nz, ColourRange cr,
                                                          int rows_per_block, int gx, int per_xcd,
@@ -509,7 +532,7 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
 #pragma unroll 1
   for (int oz = 0; oz < 3; ++oz) {
     T w[3][4][3];
-    pair_window<T>(x, st, k + oz - 1, w);
+    pair_window<T, SHFL>(x, st, k + oz - 1, w);
     pair_plane_rt<T, XF, 1 - XF>(oz, Pk, w, acca, accb);
   }
   T na[3];
@@ -526,7 +549,7 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
 // neighbour load of the pair is issued at once, across the three threads.
 // The partial sums of planes k-1 and k+1 meet the middle thread's in LDS;
 // the middle thread finishes the pair as above.
-template <typename T, int XF>
+template <typename T, int XF, bool SHFL>
 __global__ __launch_bounds__(384) void k_colour_pair_split(T* __restrict__ x,
                                                            const T* __restrict__ b, int nx,
                                                            int ny, int nz, ColourRange cr,
@@ -547,7 +570,7 @@ __global__ __launch_bounds__(384) void k_colour_pair_split(T* __restrict__ x,
   }
   {
     T w[3][4][3];
-    pair_window<T>(x, st, k + oz - 1, w);
+    pair_window<T, SHFL>(x, st, k + oz - 1, w);
     pair_plane_rt<T, XF, 1 - XF>(oz, Pk, w, acca, accb);
   }
   if (oz != 1) {
@@ -579,7 +602,7 @@ __global__ __launch_bounds__(384) void k_colour_pair_split(T* __restrict__ x,
 // neighbour row serves both nodes, so a launch issues half the neighbour
 // loads of one thread per node; each node's terms are summed in the order of
 // k_residual_gen, so the two kernels give the same values.
-template <typename T>
+template <typename T, bool SHFL>
 __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__ x,
                                                            const T* __restrict__ b,
                                                            T* __restrict__ r, int nx, int ny,
@@ -610,18 +633,34 @@ __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__
   for (int oz = 0; oz < 3; ++oz) {
     const unsigned kk = k + oz - 1;
     T w[3][4][3];  // rows j-1, j, j+1; columns i0-1 .. i0+2
+    V v[3][3];
 #pragma unroll
     for (int y = 0; y < 3; ++y) {
       const unsigned row = kk * P + ys[y] * nx;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const V v = *reinterpret_cast<const V*>(x + (c * C + row + i0));
-        w[y][1][c] = v.x;
-        w[y][2][c] = v.y;
-        w[y][0][c] = x[c * C + row + il];
-        w[y][3][c] = x[c * C + row + ir];
+        v[y][c] = *reinterpret_cast<const V*>(x + (c * C + row + i0));
+        if (!SHFL) {
+          w[y][0][c] = x[c * C + row + il];
+          w[y][3][c] = x[c * C + row + ir];
+        }
       }
     }
+    // SHFL: a row's W pairs fill W consecutive lanes (W a power of two
+    // dividing 64); the outer columns come from the neighbouring lanes
+    const int lane = static_cast<int>(__lane_id()), base = lane & ~(W - 1);
+    const int lm = base + ((p + W - 1) & (W - 1)), lp = base + ((p + 1) & (W - 1));
+#pragma unroll
+    for (int y = 0; y < 3; ++y)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        w[y][1][c] = v[y][c].x;
+        w[y][2][c] = v[y][c].y;
+        if (SHFL) {
+          w[y][0][c] = __shfl(v[y][c].y, lm);
+          w[y][3][c] = __shfl(v[y][c].x, lp);
+        }
+      }
     // the planes differ in which entries are packed: one body per plane
     auto apply = [&](auto OZ) {
       constexpr int ozc = decltype(OZ)::value;
@@ -878,6 +917,11 @@ void launch_colour_gen(T* x, const T* b, Dims d, int colour, const T* S, const T
                      d.nx, d.ny, d.nz, cr, S, Dinv);
 }
 
+bool pair_rows_in_lanes(Dims d) {
+  const int W = d.nx / 2;
+  return d.nx % 2 == 0 && W >= 1 && W <= 64 && (W & (W - 1)) == 0;
+}
+
 bool colour_pair_supported(Dims d) { return d.nx % 2 == 0 && d.nx >= 2 && d.nx <= 512; }
 
 template <typename T>
@@ -891,31 +935,47 @@ void launch_colour_pair_gen(T* x, const T* b, Dims d, int colour, const T* Pst, 
   // at 128^3)
   const int rpb = std::max(1, std::min(cr.hy, 128 / W));
   const dim3 grid(blocks_for(cr.hy, rpb), cr.nk);
+  // outer window columns by lane shuffles where a row's pairs fill a power-of-two
+  // run of lanes of one wavefront
+  const bool shfl = pair_rows_in_lanes(d);
+#define QS_PAIR(KERNEL, XF, SH, G, B, ...)                                                   \
+  hipLaunchKernelGGL((KERNEL<T, XF, SH>), G, B, 0, s, x, b, d.nx, d.ny, d.nz, cr, rpb, __VA_ARGS__)
   if (d.nx <= 64) {  // small levels: three threads per pair
     const dim3 block(rpb * W, 3);
-    if (cr.a)
-      hipLaunchKernelGGL((k_colour_pair_split<T, 1>), grid, block, 0, s, x, b, d.nx, d.ny, d.nz, cr,
-                         rpb, Pst);
+    if (cr.a && shfl)
+      QS_PAIR(k_colour_pair_split, 1, true, grid, block, Pst);
+    else if (cr.a)
+      QS_PAIR(k_colour_pair_split, 1, false, grid, block, Pst);
+    else if (shfl)
+      QS_PAIR(k_colour_pair_split, 0, true, grid, block, Pst);
     else
-      hipLaunchKernelGGL((k_colour_pair_split<T, 0>), grid, block, 0, s, x, b, d.nx, d.ny, d.nz, cr,
-                         rpb, Pst);
+      QS_PAIR(k_colour_pair_split, 0, false, grid, block, Pst);
     return;
   }
   const int threads = (rpb * W + 63) / 64 * 64;
   const int gx = static_cast<int>(grid.x), per_xcd = (gx * cr.nk + 7) / 8;
-  if (cr.a)
-    hipLaunchKernelGGL((k_colour_pair_gen<T, 1>), dim3(8 * per_xcd), dim3(threads), 0, s, x, b, d.nx,
-                       d.ny, d.nz, cr, rpb, gx, per_xcd, Pst);
+  const dim3 g1(8 * per_xcd), b1(threads);
+  if (cr.a && shfl)
+    QS_PAIR(k_colour_pair_gen, 1, true, g1, b1, gx, per_xcd, Pst);
+  else if (cr.a)
+    QS_PAIR(k_colour_pair_gen, 1, false, g1, b1, gx, per_xcd, Pst);
+  else if (shfl)
+    QS_PAIR(k_colour_pair_gen, 0, true, g1, b1, gx, per_xcd, Pst);
   else
-    hipLaunchKernelGGL((k_colour_pair_gen<T, 0>), dim3(8 * per_xcd), dim3(threads), 0, s, x, b, d.nx,
-                       d.ny, d.nz, cr, rpb, gx, per_xcd, Pst);
+    QS_PAIR(k_colour_pair_gen, 0, false, g1, b1, gx, per_xcd, Pst);
+#undef QS_PAIR
 }
 
 template <typename T>
 void launch_residual_pair_gen(const T* x, const T* b, T* r, Dims d, const T* Pst, hipStream_t s) {
   const dim3 grid(blocks_for(static_cast<long long>(d.nx / 2) * d.ny, 256), d.nz - 1);
   if (d.nz - 1 <= 0) return;
-  hipLaunchKernelGGL(k_residual_pair_gen<T>, grid, dim3(256), 0, s, x, b, r, d.nx, d.ny, d.nz, Pst);
+  if (pair_rows_in_lanes(d))
+    hipLaunchKernelGGL((k_residual_pair_gen<T, true>), grid, dim3(256), 0, s, x, b, r, d.nx, d.ny,
+                       d.nz, Pst);
+  else
+    hipLaunchKernelGGL((k_residual_pair_gen<T, false>), grid, dim3(256), 0, s, x, b, r, d.nx, d.ny,
+                       d.nz, Pst);
 }
 
 int residual_blocks(Dims d) {
