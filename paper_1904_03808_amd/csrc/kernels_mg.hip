@@ -707,8 +707,12 @@ __global__ __launch_bounds__(256) void k_residual_pair_gen(const T* __restrict__
 
 // b_c(I) = sum over the 27 fine nodes around 2I of w * r(f), w = prod (1 or 1/2).
 // One thread per coarse node; per fine row it loads the pair (2I, 2I+1) as one
-// two-wide access and 2I-1 on its own.
-template <typename T>
+// two-wide access and 2I-1 on its own, or (SHFL: the nxc coarse nodes of a row
+// are a power-of-two run of at most 64 lanes) takes 2I-1 from the lane of
+// node I-1 once all loads of the component are issued.  Rows of lanes are
+// whole (the total is a multiple of nxc), so lanes that leave early never
+// serve as a shuffle source.
+template <typename T, bool SHFL>
 __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __restrict__ bc,
                                                   T* __restrict__ xc, int nxf, int nyf, int nzf) {
   using V = typename Pair<T>::type;
@@ -735,8 +739,16 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __
       for (int dy = 0; dy < 3; ++dy) {
         const T* row = r + c * Cf + (2 * K + dz - 1) * Pf + ys[dy] * nxf;
         v[dz][dy] = *reinterpret_cast<const V*>(row + 2 * I);
-        left[dz][dy] = row[il];
+        if (!SHFL) left[dz][dy] = row[il];
       }
+    if (SHFL) {
+      const int lane = static_cast<int>(__lane_id());
+      const int src = (lane & ~(nxc - 1)) + ((I + nxc - 1) & (nxc - 1));
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) left[dz][dy] = __shfl(v[dz][dy].y, src);
+    }
     T acc = T(0);
 #pragma unroll
     for (int dz = 0; dz < 3; ++dz) {
@@ -762,8 +774,11 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ r, T* __
 // neighbourhood once, then adds plane K alone to fine plane 2K and the mean
 // of planes K and K+1 to fine plane 2K+1.  Each coarse value is loaded by the
 // threads of the rows next to it, not by every fine node around it; the fine
-// pair is read and written as one two-wide access.
-template <typename T>
+// pair is read and written as one two-wide access.  SHFL: the nxc pairs of a
+// fine row are a power-of-two run of at most 64 lanes, and the values of
+// coarse column I+1 come from the lane of pair I+1 (whole rows of lanes leave
+// together).
+template <typename T, bool SHFL>
 __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T* __restrict__ ec,
                                                      int nxf, int nyf, int nzf, int kseg) {
   using V = typename Pair<T>::type;
@@ -784,6 +799,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T*
   // x-y combination of coarse plane K for the even and the odd fine column
   // (the row j1 is loaded on even fine rows too, where it is j0, so that all
   // twelve loads are issued before any is used)
+  const int src1 = SHFL ? (static_cast<int>(__lane_id()) & ~(nxc - 1)) + ((i0 + 1) & (nxc - 1)) : 0;
   auto coarse = [&](int K, T pe[3], T po[3]) {
     T a0[3], a1[3], b0[3], b1[3];
 #pragma unroll
@@ -791,9 +807,18 @@ __global__ __launch_bounds__(256) void k_prolong_add(T* __restrict__ x, const T*
       const T* p0 = ec + c * Cc + K * Pc + j0 * nxc;
       const T* p1 = ec + c * Cc + K * Pc + j1 * nxc;
       a0[c] = p0[i0];
-      a1[c] = p0[i1];
       b0[c] = p1[i0];
-      b1[c] = p1[i1];
+      if (!SHFL) {
+        a1[c] = p0[i1];
+        b1[c] = p1[i1];
+      }
+    }
+    if (SHFL) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a1[c] = __shfl(a0[c], src1);
+        b1[c] = __shfl(b0[c], src1);
+      }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1022,8 +1047,12 @@ template <typename T>
 void launch_restrict(const T* r, T* bc, T* xc, Dims f, hipStream_t s) {
   const long long total = static_cast<long long>(f.nx / 2) * (f.ny / 2) * (f.nz / 2 - 1);
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, r, bc, xc, f.nx,
-                     f.ny, f.nz);
+  if (pair_rows_in_lanes(f))
+    hipLaunchKernelGGL((k_restrict<T, true>), dim3(blocks_for(total, 256)), dim3(256), 0, s, r, bc, xc,
+                       f.nx, f.ny, f.nz);
+  else
+    hipLaunchKernelGGL((k_restrict<T, false>), dim3(blocks_for(total, 256)), dim3(256), 0, s, r, bc,
+                       xc, f.nx, f.ny, f.nz);
 }
 
 template <typename T>
@@ -1038,8 +1067,12 @@ void launch_prolong_add(T* x, const T* ec, Dims f, hipStream_t s) {
   const int kseg = static_cast<int>(std::max<long long>(1, (nzc + want - 1) / want));
   const long long total = per * ((nzc + kseg - 1) / kseg);
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_prolong_add<T>, dim3(blocks_for(total, 256)), dim3(256), 0, s, x, ec, f.nx,
-                     f.ny, f.nz, kseg);
+  if (pair_rows_in_lanes(f))
+    hipLaunchKernelGGL((k_prolong_add<T, true>), dim3(blocks_for(total, 256)), dim3(256), 0, s, x, ec,
+                       f.nx, f.ny, f.nz, kseg);
+  else
+    hipLaunchKernelGGL((k_prolong_add<T, false>), dim3(blocks_for(total, 256)), dim3(256), 0, s, x,
+                       ec, f.nx, f.ny, f.nz, kseg);
 }
 
 void launch_reduce_sum(const double* partial, int n, double* out, double* out_host,
