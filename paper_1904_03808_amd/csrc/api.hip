@@ -165,37 +165,6 @@ qs_status hip_fail(const char* what, hipError_t e) {
 
 void set_error(const char* what) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", what); }
 
-// Packs the plane stencils of one level (packed_stencil.h).  Returns false if
-// an entry that the packing leaves out (it vanishes by the reflection
-// symmetry of the operator) exceeds 1e-12 of the largest entry of the level.
-bool pack_level(const HostLevel& hl, std::vector<double>* out) {
-  const int planes = hl.nz + 1;
-  out->assign(static_cast<size_t>(planes) * kPackedStencil, 0.0);
-  double big = 0.0, left_out = 0.0;
-  for (int k = 0; k < planes; ++k) {
-    const double* S = hl.stencil.data() + static_cast<size_t>(k) * kStencil;
-    double* P = out->data() + static_cast<size_t>(k) * kPackedStencil;
-    int n = 0;
-    for (int oz = 0; oz < 3; ++oz)
-      for (int oy = 0; oy < 3; ++oy)
-        for (int ox = 0; ox < 3; ++ox)
-          for (int c = 0; c < 3; ++c)
-            for (int d = 0; d < 3; ++d) {
-              const double v = S[(oz * 9 + oy * 3 + ox) * 9 + c * 3 + d];
-              big = std::max(big, std::fabs(v));
-              const bool centre = oz == 1 && oy == 1 && ox == 1;
-              if (centre && c == d)
-                P[kPackedCentre + c] = v;
-              else if (!centre && packed_used(oz, oy, ox, c, d))
-                P[n++] = v;
-              else
-                left_out = std::max(left_out, std::fabs(v));
-            }
-    for (int e = 0; e < 9; ++e) P[kPackedInv + e] = hl.dinv[static_cast<size_t>(k) * 9 + e];
-  }
-  return left_out <= 1e-12 * big;
-}
-
 #define QS_HIP(call)                                   \
   do {                                                 \
     const hipError_t e_ = (call);                      \

@@ -38,6 +38,11 @@ void fine_stencil(int nz, double h, double lam, double mu, std::vector<double>* 
 // composing stencils on the infinite x/y lattice.
 void galerkin_stencil(const std::vector<double>& Sf, int nzf, std::vector<double>* Sc);
 
+// The plane stencils of one level in the packed form of packed_stencil.h
+// ((nz + 1) * kPackedStencil entries).  Returns false if an entry the packing
+// leaves out exceeds 1e-12 of the largest entry of the level.
+bool pack_level(const HostLevel& hl, std::vector<double>* out);
+
 // Full hierarchy; returns 0, or -2 for a shape error.
 int build_hierarchy(int nx, int ny, int nz, double h, double lam, double mu,
                     int min_coarse_nz, HostHierarchy* H);

@@ -15,7 +15,9 @@
 // entries of the centre block (its off-diagonal entries vanish by the same
 // symmetry) and two pad entries.
 // Kernels walk the same loops with a running index, which the compiler
-// resolves to constants once the loops are unrolled.
+// resolves to constants once the loops are unrolled.  Plain C++ (constexpr
+// functions serve device code as they are), so that the host packer and its
+// host check use the same definitions.
 #pragma once
 
 namespace qs {
@@ -25,7 +27,7 @@ constexpr int kPackedEntries = 150;  // off-centre entries
 constexpr int kPackedInv = 150;      // 9 entries of the inverse centre block
 constexpr int kPackedCentre = 159;   // 3 diagonal entries of the centre block
 
-__host__ __device__ constexpr bool packed_used(int oz, int oy, int ox, int c, int d) {
+constexpr bool packed_used(int oz, int oy, int ox, int c, int d) {
   if (oz == 1 && oy == 1 && ox == 1) return false;
   if (c == d) return true;
   const int oc = c == 0 ? ox : (c == 1 ? oy : oz);
@@ -34,7 +36,7 @@ __host__ __device__ constexpr bool packed_used(int oz, int oy, int ox, int c, in
 }
 
 // Position of the first packed entry of block (oz, oy, ox).
-__host__ __device__ constexpr int packed_block_start(int oz, int oy, int ox) {
+constexpr int packed_block_start(int oz, int oy, int ox) {
   int n = 0;
   for (int t = 0; t < oz * 9 + oy * 3 + ox; ++t)
     for (int c = 0; c < 3; ++c)
@@ -42,7 +44,7 @@ __host__ __device__ constexpr int packed_block_start(int oz, int oy, int ox) {
   return n;
 }
 // Packed entries of the planes oz' < oz (59 for oz = 1, 91 for oz = 2).
-__host__ __device__ constexpr int packed_plane_start(int oz) { return packed_block_start(oz, 0, 0); }
+constexpr int packed_plane_start(int oz) { return packed_block_start(oz, 0, 0); }
 static_assert(packed_plane_start(1) == 59 && packed_plane_start(2) == 91 &&
                   packed_block_start(2, 2, 2) + 9 == kPackedEntries,
               "packed stencil layout");

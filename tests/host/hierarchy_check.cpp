@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../paper_1904_03808_amd/csrc/hierarchy.h"
+#include "../../paper_1904_03808_amd/csrc/packed_stencil.h"
 
 namespace {
 
@@ -59,6 +60,65 @@ bool check_level(const qs::HostLevel& L, int level) {
   return true;
 }
 
+// The packed form (packed_stencil.h) of every plane: the entries it keeps
+// are the stencil's, in order, 150 per plane, with the inverse and the centre
+// diagonal after them; the entries it leaves out (couplings between
+// different components where the offset along one of them is zero, which
+// the reflection symmetry of the operator makes vanish) are below 1e-14 of
+// the largest entry; and a planted non-zero in a left-out place is refused.
+bool check_packing(const qs::HostLevel& L, int level) {
+  std::vector<double> P;
+  if (!qs::pack_level(L, &P)) {
+    std::printf("level %d: pack_level refused the hierarchy\n", level);
+    return false;
+  }
+  double scale = 0.0;
+  for (double v : L.stencil) scale = std::fmax(scale, std::fabs(v));
+  for (int k = 1; k < L.nz; ++k) {
+    const double* S = L.stencil.data() + static_cast<size_t>(k) * qs::kStencil;
+    const double* Q = P.data() + static_cast<size_t>(k) * qs::kPackedStencil;
+    int n = 0;
+    for (int oz = 0; oz < 3; ++oz)
+      for (int oy = 0; oy < 3; ++oy)
+        for (int ox = 0; ox < 3; ++ox)
+          for (int c = 0; c < 3; ++c)
+            for (int d = 0; d < 3; ++d) {
+              const double v = S[(oz * 9 + oy * 3 + ox) * 9 + c * 3 + d];
+              const bool centre = oz == 1 && oy == 1 && ox == 1;
+              bool good = true;
+              if (centre && c == d)
+                good = Q[qs::kPackedCentre + c] == v;
+              else if (!centre && qs::packed_used(oz, oy, ox, c, d))
+                good = Q[n++] == v;
+              else
+                good = std::fabs(v) <= 1e-14 * scale;
+              if (!good) {
+                std::printf("level %d: packed entry wrong at k=%d o=(%d,%d,%d) c=%d d=%d\n", level, k,
+                            oz, oy, ox, c, d);
+                return false;
+              }
+            }
+    if (n != qs::kPackedEntries) {
+      std::printf("level %d: %d packed entries\n", level, n);
+      return false;
+    }
+    for (int e = 0; e < 9; ++e)
+      if (Q[qs::kPackedInv + e] != L.dinv[static_cast<size_t>(k) * 9 + e]) {
+        std::printf("level %d: packed inverse wrong at k=%d\n", level, k);
+        return false;
+      }
+  }
+  // an x-y coupling at the face offset (0, 0, +1) may not be packed away
+  qs::HostLevel bad = L;
+  const int k = L.nz / 2;
+  bad.stencil[static_cast<size_t>(k) * qs::kStencil + (2 * 9 + 1 * 3 + 1) * 9 + 0 * 3 + 1] = 1e-6 * scale;
+  if (qs::pack_level(bad, &P)) {
+    std::printf("level %d: a planted coupling was packed away\n", level);
+    return false;
+  }
+  return true;
+}
+
 }  // namespace
 
 int main() {
@@ -77,7 +137,9 @@ int main() {
       return 1;
     }
     for (size_t l = 0; l < H.levels.size(); ++l)
-      if (!check_level(H.levels[l], static_cast<int>(l))) return 1;
+      if (!check_level(H.levels[l], static_cast<int>(l)) ||
+          !check_packing(H.levels[l], static_cast<int>(l)))
+        return 1;
     const int n = H.n_coarse;
     for (int r = 0; r < n; ++r)
       for (int c = 0; c < r; ++c)

@@ -3,7 +3,10 @@ fine and Galerkin stencils, centre-block and coarsest inverses) built with
 g++ under AddressSanitizer and UndefinedBehaviorSanitizer and run on grid
 shapes the tests and workloads use: no memory or UB error, K symmetric on
 every level, wall rows zero, centre inverses exact, the coarsest inverse
-symmetric, and uncoarsenable shapes refused."""
+symmetric, uncoarsenable shapes refused, and the packed stencils the coarse
+kernels read: the entries they leave out (cross-component couplings that
+vanish by reflection symmetry) below 1e-14 of the largest on every level,
+the kept ones in order, and a planted coupling refused."""
 import os
 import shutil
 import subprocess
