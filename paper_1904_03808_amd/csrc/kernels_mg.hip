@@ -461,18 +461,21 @@ __device__ __forceinline__ void apply_inv(const T* __restrict__ Di, const T acc[
 // The b-node's x neighbours of colour a (the own a-node na and, from LDS xa,
 // that of the pair on the side away from it), its last terms, its new value,
 // and the store of the pair.
-template <typename T, int XF>
+template <typename T, int XF, bool SHFL>
 __device__ __forceinline__ void pair_finish(T* __restrict__ x, const PairSite<T>& st,
                                             const T* __restrict__ Pk, const T (*xa)[256], int tid,
                                             const T na[3], T accb[3]) {
   using V = typename Pair<T>::type;
   const int pn = XF ? (st.p == 0 ? st.W - 1 : st.p - 1) : (st.p == st.W - 1 ? 0 : st.p + 1);
   const int tn = st.active ? st.rr * st.W + pn : tid;
+  // SHFL: the neighbour pair is the lane pn of the row's run of lanes, and
+  // its new a-node comes by a shuffle (xa is not used)
+  const int ln = SHFL ? (static_cast<int>(__lane_id()) & ~(st.W - 1)) + pn : 0;
   T side[2][3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     side[XF][c] = na[c];  // XF = 0: left neighbour (i0) is own; XF = 1: right (i0+1)
-    side[1 - XF][c] = xa[c][tn];
+    side[1 - XF][c] = SHFL ? __shfl(na[c], ln) : xa[c][tn];
   }
 #pragma unroll
   for (int s2 = 0; s2 < 2; ++s2) {
@@ -498,7 +501,9 @@ __device__ __forceinline__ void pair_finish(T* __restrict__ x, const PairSite<T>
 }
 
 // One thread per column pair: the three neighbour planes in a loop that is
-// not unrolled, each visit issuing its 36 loads together (128^3 and larger).
+// not unrolled, each visit issuing its loads together (128^3 and larger).
+// SHFL: the outer window columns and the neighbour pair's new a-node come by
+// lane shuffles, with no LDS exchange and no barrier.
 // The grid is one-dimensional, gx row blocks times the colour's planes, in
 // an XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, and XCD
 // x takes the contiguous range [x per_xcd, (x+1) per_xcd) of (plane, row
@@ -537,10 +542,12 @@ __global__ __launch_bounds__(256) void k_colour_pair_gen(T* __restrict__ x, cons
   }
   T na[3];
   apply_inv<T>(Pk + kPackedInv, acca, na);
+  if (!SHFL) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
-  __syncthreads();
-  pair_finish<T, XF>(x, st, Pk, xa, tid, na, accb);
+    for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
+    __syncthreads();
+  }
+  pair_finish<T, XF, SHFL>(x, st, Pk, xa, tid, na, accb);
 }
 
 // The same two colours with three threads per column pair, one per
@@ -590,11 +597,13 @@ __global__ __launch_bounds__(384) void k_colour_pair_split(T* __restrict__ x,
       accb[c] = bb + part[0][1][c][tid] + accb[c] + part[1][1][c][tid];
     }
     apply_inv<T>(Pk + kPackedInv, acca, na);
+    if (!SHFL) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
+      for (int c = 0; c < 3; ++c) xa[c][tid] = na[c];
+    }
   }
-  __syncthreads();
-  if (oz == 1) pair_finish<T, XF>(x, st, Pk, xa, tid, na, accb);
+  if (!SHFL) __syncthreads();
+  if (oz == 1) pair_finish<T, XF, SHFL>(x, st, Pk, xa, tid, na, accb);
 }
 
 // Coarse residual r = b - A x (V-cycle form: no norm) for the column pair
