@@ -228,8 +228,9 @@ int build_hierarchy(int nx, int ny, int nz, double h, double lam, double mu,
 }
 
 // Packs the plane stencils of one level (packed_stencil.h).  Returns false if
-// an entry that the packing leaves out (it vanishes by the reflection
-// symmetry of the operator) exceeds 1e-12 of the largest entry of the level.
+// an entry that the packing leaves out (a cross-component coupling at a zero
+// offset along one of its components, zero in exact arithmetic) exceeds 1e-12
+// of the largest entry of the level.
 bool pack_level(const HostLevel& hl, std::vector<double>* out) {
   const int planes = hl.nz + 1;
   out->assign(static_cast<size_t>(planes) * kPackedStencil, 0.0);

@@ -2,18 +2,20 @@
 //
 // The full stencil of plane k holds 27 blocks of 3x3: block (oz, oy, ox)
 // (each 0..2 for the offsets -1, 0, +1) couples component c of a node to
-// component d of the node at that offset.  The operator is even under the
-// reflection of x, y or z together with the sign flip of the matching
-// velocity component, and the trilinear transfers keep that symmetry, so an
-// entry with c != d vanishes wherever the offset along c or along d is zero
-// (on the grids in use such entries are rounding noise, below 1e-16 of the
+// component d of the node at that offset.  The fine operator couples c to
+// d != c only through (lambda + mu) times the product of the central first
+// differences along c and along d, each antisymmetric (also restricted to the
+// interior planes); the transfers are tensor products, and a Galerkin product
+// B^T D B of an antisymmetric factor stays antisymmetric.  So on every level
+// an entry with c != d vanishes wherever the offset along c or along d is
+// zero (on the grids in use such entries are rounding noise, below 1e-16 of the
 // largest entry; the library checks this at setup).  Apart from the centre
 // block, what remains is 150 entries per plane:
 //   faces 6 x 3 (diagonal), edges 12 x 5, corners 8 x 9,
 // stored in the loop order (oz, oy, ox, c, d) with unused entries skipped,
 // followed by the 9 entries of the inverse centre block, the 3 diagonal
-// entries of the centre block (its off-diagonal entries vanish by the same
-// symmetry) and two pad entries.
+// entries of the centre block (its off-diagonal entries vanish for the same
+// reason) and two pad entries.
 // Kernels walk the same loops with a running index, which the compiler
 // resolves to constants once the loops are unrolled.  Plain C++ (constexpr
 // functions serve device code as they are), so that the host packer and its

@@ -64,7 +64,7 @@ bool check_level(const qs::HostLevel& L, int level) {
 // are the stencil's, in order, 150 per plane, with the inverse and the centre
 // diagonal after them; the entries it leaves out (couplings between
 // different components where the offset along one of them is zero, which
-// the reflection symmetry of the operator makes vanish) are below 1e-14 of
+// vanish in exact arithmetic) are below 1e-14 of
 // the largest entry; and a planted non-zero in a left-out place is refused.
 bool check_packing(const qs::HostLevel& L, int level) {
   std::vector<double> P;

@@ -4,8 +4,9 @@ g++ under AddressSanitizer and UndefinedBehaviorSanitizer and run on grid
 shapes the tests and workloads use: no memory or UB error, K symmetric on
 every level, wall rows zero, centre inverses exact, the coarsest inverse
 symmetric, uncoarsenable shapes refused, and the packed stencils the coarse
-kernels read: the entries they leave out (cross-component couplings that
-vanish by reflection symmetry) below 1e-14 of the largest on every level,
+kernels read: the entries they leave out (cross-component couplings at a
+zero offset along one of the components, zero in exact arithmetic) below
+1e-14 of the largest on every level,
 the kept ones in order, and a planted coupling refused."""
 import os
 import shutil

@@ -75,6 +75,40 @@ def test_galerkin_two_ways(nz):
     assert np.abs(cb - np.einsum("kcc->kc", cb)[:, :, None] * np.eye(3)).max() < 1e-12 * np.abs(cb).max()
 
 
+@pytest.mark.parametrize("n,mc", [((32, 32, 32), 2), ((48, 40, 32), 4)])
+def test_galerkin_cross_couplings_vanish_on_zero_offsets(n, mc):
+    """On every level, an entry coupling component c to component d != c is
+    zero (to rounding) wherever the offset along c or along d is zero.  The
+    fine operator's cross-component part is (lam+mu) times the product of the
+    central first differences along c and along d, each antisymmetric (also
+    restricted to the interior planes); the transfers are tensor products, and
+    a Galerkin product B^T D B of an antisymmetric factor is antisymmetric, so
+    its zero offset vanishes on every level.  The coarse-level kernels leave
+    these entries out.  (A one-sided mixed difference in the fine operator
+    fails this test.)"""
+    nx, ny, nz = n
+    o = MGOracle(nx, ny, nz, 1.0 / nz, LAM, MU, min_coarse_nz=mc)
+    assert len(o.levels) >= 4
+    for L in o.levels:
+        A = L.A
+        big = np.abs(A).max()
+        worst = 0.0
+        for oz in range(3):
+            for oy in range(3):
+                for ox in range(3):
+                    off = (ox - 1, oy - 1, oz - 1)
+                    for c in range(3):
+                        for d in range(3):
+                            if c != d and (off[c] == 0 or off[d] == 0):
+                                worst = max(worst, np.abs(A[:, oz, oy, ox, c, d]).max())
+        assert worst <= 1e-14 * big, (L.nx, L.ny, L.nz, worst / big)
+        # and the cross couplings kept are not all zero on the coarse levels
+        # (corner offsets, on planes whose neighbours are interior; the fine
+        # operator has no corner couplings)
+        if L is not o.levels[0] and L.nz >= 4:
+            assert np.abs(A[2:L.nz - 1, 2, 2, 2, 0, 1]).max() > 1e-6 * big
+
+
 def test_colour_pass_zeroes_colour_residual():
     """After updating colour c, the residual vanishes at every node of colour c."""
     rng = np.random.default_rng(5)
