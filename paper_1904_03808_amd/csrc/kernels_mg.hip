@@ -328,11 +328,14 @@ struct Pair<double> {
 // of colour b only along x within their row and plane, so a thread owns the
 // column pair (2p, 2p+1) of one row and plane: it updates its a-node from the
 // old values, then its b-node once both x neighbours of colour a (its own and
-// the one of pair p+1 or p-1) are new.  Those come through LDS; a workgroup
+// the one of pair p+1 or p-1) are new.  Where the column pairs of a row fill
+// a power-of-two run of at most 64 lanes, that neighbour's new a-node comes by
+// a lane shuffle; otherwise it comes through LDS.  Either way a workgroup
 // holds whole rows, so the periodic neighbour in x is always present.  Every
 // other term of the b-node uses values that neither update changes, and is
 // summed while the a-node is.  Neighbour values of both nodes are read as
-// pairs plus the two outer columns (four columns per row), so a launch moves
+// pairs plus the two outer columns (four columns per row; the outer two, too,
+// come by shuffles where the row fits that run of lanes), so a launch issues
 // half the loads of two single-colour launches.
 //
 // A workgroup lies in one plane, so the plane's packed stencil (150 entries
@@ -458,9 +461,9 @@ __device__ __forceinline__ void apply_inv(const T* __restrict__ Di, const T acc[
   for (int c = 0; c < 3; ++c) out[c] = Di[c * 3] * acc[0] + Di[c * 3 + 1] * acc[1] + Di[c * 3 + 2] * acc[2];
 }
 
-// The b-node's x neighbours of colour a (the own a-node na and, from LDS xa,
-// that of the pair on the side away from it), its last terms, its new value,
-// and the store of the pair.
+// The b-node's x neighbours of colour a (the own a-node na and that of the
+// pair on the side away from it, by a shuffle or from LDS xa), its last terms,
+// its new value, and the store of the pair.
 template <typename T, int XF, bool SHFL>
 __device__ __forceinline__ void pair_finish(T* __restrict__ x, const PairSite<T>& st,
                                             const T* __restrict__ Pk, const T (*xa)[256], int tid,
