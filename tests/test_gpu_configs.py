@@ -52,7 +52,8 @@ def test_config2_residual_at_256(prec):
     """256^3 solve to 1e-10: the oracle's own operator confirms the residual."""
     n = 256
     g = solver(n, precision=prec)
-    sig = dev(stress_field(n, n, n, 2))
+    sig_h = stress_field(n, n, n, 2)
+    sig = dev(sig_h)
     b = g.rhs(sig, 1.0)
     del sig
     x = torch.zeros_like(b)
@@ -62,8 +63,13 @@ def test_config2_residual_at_256(prec):
     r = bb - apply_elastic(xb, 1.0 / n, LAM, MU)
     rel = np.linalg.norm(r[:, 1:n]) / np.linalg.norm(bb[:, 1:n])
     assert rel <= 1.2e-10, rel
-    # the right-hand side itself at sampled nodes: D_h sigma (oracle) on a patch
-    assert np.isfinite(rel)
+    # the right-hand side itself at sampled nodes: the oracle's D_h sigma on
+    # the 2 x 2 x 2 cells around each node (periodic in x and y)
+    rng = np.random.default_rng(32)
+    for k, j, i in zip(rng.integers(1, n, 256), rng.integers(0, n, 256), rng.integers(0, n, 256)):
+        cells = sig_h[np.ix_(range(6), [k - 1, k], [(j - 1) % n, j], [(i - 1) % n, i])]
+        want = ostz.rhs(cells, 1.0 / n, 1.0)[:, 1, 1, 1]
+        assert np.abs(bb[:, k, j, i] - want).max() <= 1e-13 * np.abs(want).max() + 1e-300, (k, j, i)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
@@ -90,6 +96,48 @@ def test_config2_error_against_oracle_solution_256(prec):
     nerr = abs(torch.linalg.vector_norm(x).item() - ref["x_norm"]) / ref["x_norm"]
     print("%s: sampled error %.3e, norm error %.3e" % (prec, err, nerr))
     assert err <= 1e-8 and nerr <= 1e-8, (err, nerr)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
+def test_fine_sweep_256_sampled_nodes(prec):
+    """One smoothing sweep of the 256^3 fine level through qs_smooth, the call
+    and launch configuration the benchmark times (two row-parity half sweeps,
+    z-segments chosen for 256^3, row groups dealt to the XCDs), checked by the
+    oracle node by node (Gauss-Seidel from the old and new neighbour values,
+    tests/sweep_sample.py) at 3072 nodes: the planes at and next to segment
+    ends and walls, the first and last rows and columns (wrapped neighbours),
+    and random nodes.  Also: the wall planes are unchanged, bit for bit, and
+    every interior node moved (no row group or segment left out)."""
+    from oracle.multigrid import DEFAULT_ORDER, fine_stencil
+    from sweep_sample import sweep_at_nodes
+    n = 256
+    g = solver(n, precision=prec)
+    assert g.levels == 6
+    rng = np.random.default_rng(31)
+    dt = np.float64 if prec == "fp64" else np.float32
+    x = rng.standard_normal((3, n + 1, n, n)).astype(dt)
+    b = rng.standard_normal((3, n + 1, n, n)).astype(dt)
+    xd = torch.from_numpy(x).to("cuda")
+    g.smooth(0, xd, torch.from_numpy(b).to("cuda"), 1)
+    xn = host(xd)
+    del xd
+    assert np.array_equal(xn[:, 0], x[:, 0]) and np.array_equal(xn[:, n], x[:, n])
+    still = np.count_nonzero(xn[:, 1:n] == x[:, 1:n])
+    assert still <= (0 if prec == "fp64" else 1000), still
+    ks = [1, 2, 3, 15, 16, 17, 31, 32, 33, 34, 63, 64, 65, 66, 95, 96, 97, 127, 128, 129,
+          191, 192, 193, 223, 224, 225, 253, 254, 255]
+    js = [0, 1, 2, 3, 4, 5, 126, 127, 128, 129, 250, 251, 252, 253, 254, 255]
+    is_ = [0, 1, 2, 3, 126, 127, 128, 129, 252, 253, 254, 255]
+    nodes = list(zip(rng.choice(ks, 2048), rng.choice(js, 2048), rng.choice(is_, 2048)))
+    nodes += list(zip(rng.integers(1, n, 1024), rng.integers(0, n, 1024), rng.integers(0, n, 1024)))
+    assert len({(i & 1, j & 1, k & 1) for k, j, i in nodes}) == 8
+    A = fine_stencil(n, 1.0 / n, LAM, MU)
+    want = sweep_at_nodes(A, x.astype(np.float64), xn.astype(np.float64), b.astype(np.float64),
+                          nodes, DEFAULT_ORDER)
+    got = np.array([xn[:, k, j, i] for k, j, i in nodes], dtype=np.float64)
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print("%s: sampled sweep error %.3e, unchanged interior values %d" % (prec, err, still))
+    assert err < (1e-13 if prec == "fp64" else 2e-6), err
 
 
 def test_config2_at_512():

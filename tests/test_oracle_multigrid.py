@@ -227,3 +227,39 @@ def test_mg_matches_sparse_direct_on_flat_grids(shape, levels):
     assert info["converged"]
     xd = direct_solve(b, x0, h, LAM, MU)
     assert np.abs(x - xd).max() <= 1e-11 * np.abs(xd).max()
+
+
+@pytest.mark.parametrize("lvl", [0, 1])
+def test_sweep_at_nodes_matches_the_oracle_sweep(lvl):
+    """The node-by-node evaluation of one sweep (which checks the GPU sweep at
+    full size on sampled nodes) reproduces the oracle's colour-major sweep at
+    every interior node of a fine and a Galerkin level, and notices a sweep
+    run in another colour order and a single wrong node."""
+    from sweep_sample import sweep_at_nodes
+    rng = np.random.default_rng(21)
+    mg = MGOracle(16, 12, 8, 1.0 / 8, LAM, MU, min_coarse_nz=2)
+    L = mg.levels[lvl]
+    x = rng.standard_normal(L.shape)
+    b = rng.standard_normal(L.shape)
+    xn = x.copy()
+    L.sweep(xn, b, DEFAULT_ORDER)
+    nodes = [(k, j, i) for k in range(1, L.nz) for j in range(L.ny) for i in range(L.nx)]
+    got = sweep_at_nodes(L.A, x, xn, b, nodes, DEFAULT_ORDER)
+    want = np.array([xn[:, k, j, i] for (k, j, i) in nodes])
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    # a sweep in the ascending colour order is not the default sweep
+    xa = x.copy()
+    L.sweep(xa, b, [(c & 1, (c >> 1) & 1, (c >> 2) & 1) for c in range(8)])
+    got = sweep_at_nodes(L.A, x, xa, b, nodes, DEFAULT_ORDER)
+    want = np.array([xa[:, k, j, i] for (k, j, i) in nodes])
+    assert np.abs(got - want).max() > 1e-3 * np.abs(want).max()
+    # one wrong new value (colour 0, the first visited) shows at that node
+    # and at every neighbour coupled to it, all of later colours: on the fine
+    # level a y component reaches the 6 face and the 8 xy and yz edge
+    # neighbours, on a Galerkin level all 26
+    xw = xn.copy()
+    xw[1, 2, 4, 6] += 1e-6
+    got = sweep_at_nodes(L.A, x, xw, b, nodes, DEFAULT_ORDER)
+    want = np.array([xw[:, k, j, i] for (k, j, i) in nodes])
+    bad = {nodes[t] for t in np.flatnonzero(np.abs(got - want).max(axis=1) > 1e-12)}
+    assert (2, 4, 6) in bad and len(bad) == 1 + (14 if lvl == 0 else 26)
