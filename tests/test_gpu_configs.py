@@ -99,44 +99,57 @@ def test_config2_error_against_oracle_solution_256(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
-def test_fine_sweep_256_sampled_nodes(prec):
-    """One smoothing sweep of the 256^3 fine level through qs_smooth, the call
-    and launch configuration the benchmark times (two row-parity half sweeps,
-    z-segments chosen for 256^3, row groups dealt to the XCDs), checked by the
-    oracle node by node (Gauss-Seidel from the old and new neighbour values,
-    tests/sweep_sample.py) at 3072 nodes: the planes at and next to segment
-    ends and walls, the first and last rows and columns (wrapped neighbours),
-    and random nodes.  Also: the wall planes are unchanged, bit for bit, and
-    every interior node moved (no row group or segment left out)."""
-    from oracle.multigrid import DEFAULT_ORDER, fine_stencil
+@pytest.mark.parametrize("level", [0, 1])
+def test_sweep_256_sampled_nodes(level, prec):
+    """One smoothing sweep of the 256^3 hierarchy's fine level (level 0: the
+    two row-parity half sweeps, z-segments chosen for 256^3, row groups dealt
+    to the XCDs) and of its 128^3 level (level 1: four two-colour launches in
+    their XCD-ordered grid, packed Galerkin stencils), through qs_smooth, the
+    call and launch configuration the benchmark times, checked by the oracle
+    node by node (Gauss-Seidel from the old and new neighbour values with the
+    oracle's own stencils, tests/sweep_sample.py) at 3072 nodes: planes at and
+    next to segment ends and walls, the first and last rows and columns
+    (wrapped neighbours), and random nodes.  Also: the wall planes are
+    unchanged, bit for bit, and every interior node moved (no row group,
+    segment or plane left out)."""
+    from oracle.multigrid import DEFAULT_ORDER, fine_stencil, galerkin_stencil
     from sweep_sample import sweep_at_nodes
     n = 256
     g = solver(n, precision=prec)
     assert g.levels == 6
-    rng = np.random.default_rng(31)
+    m = n >> level
+    assert g.level_dims(level) == (m, m, m)
+    rng = np.random.default_rng(31 + level)
     dt = np.float64 if prec == "fp64" else np.float32
-    x = rng.standard_normal((3, n + 1, n, n)).astype(dt)
-    b = rng.standard_normal((3, n + 1, n, n)).astype(dt)
+    x = rng.standard_normal((3, m + 1, m, m))
+    if level > 0:
+        x[:, 0] = 0.0  # coarse corrections have zero walls
+        x[:, m] = 0.0
+    x = x.astype(dt)
+    b = rng.standard_normal((3, m + 1, m, m)).astype(dt)
     xd = torch.from_numpy(x).to("cuda")
-    g.smooth(0, xd, torch.from_numpy(b).to("cuda"), 1)
+    g.smooth(level, xd, torch.from_numpy(b).to("cuda"), 1)
     xn = host(xd)
     del xd
-    assert np.array_equal(xn[:, 0], x[:, 0]) and np.array_equal(xn[:, n], x[:, n])
-    still = np.count_nonzero(xn[:, 1:n] == x[:, 1:n])
+    assert np.array_equal(xn[:, 0], x[:, 0]) and np.array_equal(xn[:, m], x[:, m])
+    still = np.count_nonzero(xn[:, 1:m] == x[:, 1:m])
     assert still <= (0 if prec == "fp64" else 1000), still
-    ks = [1, 2, 3, 15, 16, 17, 31, 32, 33, 34, 63, 64, 65, 66, 95, 96, 97, 127, 128, 129,
-          191, 192, 193, 223, 224, 225, 253, 254, 255]
-    js = [0, 1, 2, 3, 4, 5, 126, 127, 128, 129, 250, 251, 252, 253, 254, 255]
-    is_ = [0, 1, 2, 3, 126, 127, 128, 129, 252, 253, 254, 255]
+    ks = [k for k in (1, 2, 3, 15, 16, 17, 31, 32, 33, 34, 63, 64, 65, 66, 95, 96, 97, 127, 128,
+                      129, 191, 192, 193, 223, 224, 225) if k < m - 3] + [m - 3, m - 2, m - 1]
+    js = [0, 1, 2, 3, 4, 5, m // 2 - 2, m // 2 - 1, m // 2, m // 2 + 1] + list(range(m - 6, m))
+    is_ = [0, 1, 2, 3, m // 2 - 2, m // 2 - 1, m // 2, m // 2 + 1] + list(range(m - 4, m))
     nodes = list(zip(rng.choice(ks, 2048), rng.choice(js, 2048), rng.choice(is_, 2048)))
-    nodes += list(zip(rng.integers(1, n, 1024), rng.integers(0, n, 1024), rng.integers(0, n, 1024)))
+    nodes += list(zip(rng.integers(1, m, 1024), rng.integers(0, m, 1024), rng.integers(0, m, 1024)))
     assert len({(i & 1, j & 1, k & 1) for k, j, i in nodes}) == 8
     A = fine_stencil(n, 1.0 / n, LAM, MU)
+    if level == 1:
+        A = galerkin_stencil(A, n)
     want = sweep_at_nodes(A, x.astype(np.float64), xn.astype(np.float64), b.astype(np.float64),
                           nodes, DEFAULT_ORDER)
     got = np.array([xn[:, k, j, i] for k, j, i in nodes], dtype=np.float64)
     err = np.abs(got - want).max() / np.abs(want).max()
-    print("%s: sampled sweep error %.3e, unchanged interior values %d" % (prec, err, still))
+    print("level %d %s: sampled sweep error %.3e, unchanged interior values %d"
+          % (level, prec, err, still))
     assert err < (1e-13 if prec == "fp64" else 2e-6), err
 
 
