@@ -98,6 +98,34 @@ def test_config2_error_against_oracle_solution_256(prec):
     assert err <= 1e-8 and nerr <= 1e-8, (err, nerr)
 
 
+def test_vcycles_256_match_the_oracle():
+    """The first two FP64 V-cycles of the benchmark's 256^3 solve (x = 0, b =
+    D_h sigma of the seed-2 stress, computed by the oracle; six levels, every
+    kernel of the cycle in the launch configuration the benchmark times)
+    equal the oracle's V-cycles element by element (<= 1e-12 of the largest
+    value), and the relative residual after them agrees to 1e-9.  The oracle
+    takes about half a minute per cycle at this size."""
+    from oracle.multigrid import MGOracle
+    n = 256
+    g = solver(n, precision="fp64")
+    o = MGOracle(n, n, n, 1.0 / n, LAM, MU)
+    assert g.levels == len(o.levels) == 6
+    b = ostz.rhs(stress_field(n, n, n, 2), 1.0 / n, 1.0)
+    bd = dev(b)
+    x = np.zeros_like(b)
+    nb = o.lifted_rhs_norm(b, x)
+    for k in (1, 2):
+        xd = torch.zeros_like(bd)
+        info = g.solve(bd, xd, rtol=0.0, max_cycles=k)
+        assert info.cycles == k
+        o.vcycle(x, b)
+        err = np.abs(host(xd) - x).max() / np.abs(x).max()
+        print("cycle %d: largest difference %.3e of the largest value" % (k, err))
+        assert err <= 1e-12, (k, err)
+    rel = float(np.linalg.norm(o.residual(x, b)[:, 1:-1])) / nb
+    assert abs(info.rel_res - rel) <= 1e-9 * rel, (info.rel_res, rel)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
 @pytest.mark.parametrize("level", [0, 1])
 def test_sweep_256_sampled_nodes(level, prec):
