@@ -127,57 +127,63 @@ def test_vcycles_256_match_the_oracle():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
-@pytest.mark.parametrize("n,level", [(256, 0), (256, 1), (512, 0)])
-def test_sweep_sampled_nodes_full_size(n, level, prec):
+@pytest.mark.parametrize("shape,mc,level", [((256, 256, 256), 8, 0), ((256, 256, 256), 8, 1),
+                                            ((512, 512, 512), 8, 0), ((768, 768, 384), 4, 0)],
+                         ids=["256", "256-level1", "512", "768x768x384"])
+def test_sweep_sampled_nodes_full_size(shape, mc, level, prec):
     """One smoothing sweep of the fine level of the 256^3 and 512^3
-    hierarchies (the two row-parity half sweeps, z-segments chosen for the
-    size, row groups dealt to the XCDs) and of the 256^3 hierarchy's 128^3
-    level (four two-colour launches in their XCD-ordered grid, packed Galerkin
-    stencils), through qs_smooth, the call and launch configuration the
-    benchmark times, checked by the oracle node by node (Gauss-Seidel from the
-    old and new neighbour values with the oracle's own stencils,
-    tests/sweep_sample.py) at 3072 nodes: planes at and next to every multiple
-    of 16 (segment ends) and the walls, the first, middle and last rows and
-    columns (wrapped neighbours), and random nodes.  Also: the wall planes are
-    unchanged, bit for bit, and every interior node moved (no row group,
-    segment or plane left out)."""
+    hierarchies and of the paper's largest grid, 768 x 768 x 384 (the two
+    row-parity half sweeps, z-segments chosen for the size, row groups dealt
+    to the XCDs; 768-wide rows as one row per workgroup in FP32 and split over
+    two workgroups in FP64), and of the 256^3 hierarchy's 128^3 level (four
+    two-colour launches in their XCD-ordered grid, packed Galerkin stencils),
+    through qs_smooth, the call and launch configuration the benchmark times,
+    checked by the oracle node by node (Gauss-Seidel from the old and new
+    neighbour values with the oracle's own stencils, tests/sweep_sample.py)
+    at 3072 nodes: planes at and next to every multiple of 16 (segment ends)
+    and the walls, the first, middle and last rows and columns (wrapped
+    neighbours), and random nodes.  Also: the wall planes are unchanged, bit
+    for bit, and every interior node moved (no row group, segment or plane
+    left out)."""
     from oracle.multigrid import DEFAULT_ORDER, fine_stencil, galerkin_stencil
+    from paper_1904_03808_amd.qsmg import MGSolver
     from sweep_sample import sweep_at_nodes
-    g = solver(n, precision=prec)
-    assert g.levels == {256: 6, 512: 7}[n]
-    m = n >> level
-    assert g.level_dims(level) == (m, m, m)
-    rng = np.random.default_rng(31 + level + n)
+    nx, ny, nz = shape
+    g = MGSolver(nx, ny, nz, 1.0 / nz, LAM, MU, min_coarse_nz=mc, precision=prec)
+    mx, my, mz = nx >> level, ny >> level, nz >> level
+    assert g.level_dims(level) == (mx, my, mz)
+    rng = np.random.default_rng(31 + level + nx)
     dt = np.float64 if prec == "fp64" else np.float32
-    x = rng.standard_normal((3, m + 1, m, m), dtype=dt)
+    x = rng.standard_normal((3, mz + 1, my, mx), dtype=dt)
     if level > 0:
         x[:, 0] = 0.0  # coarse corrections have zero walls
-        x[:, m] = 0.0
-    b = rng.standard_normal((3, m + 1, m, m), dtype=dt)
+        x[:, mz] = 0.0
+    b = rng.standard_normal((3, mz + 1, my, mx), dtype=dt)
     xd = torch.from_numpy(x).to("cuda")
     g.smooth(level, xd, torch.from_numpy(b).to("cuda"), 1)
     xn = host(xd)
     del xd
+    g.close()
     torch.cuda.empty_cache()
-    assert np.array_equal(xn[:, 0], x[:, 0]) and np.array_equal(xn[:, m], x[:, m])
-    still = int(sum(np.count_nonzero(xn[:, k] == x[:, k]) for k in range(1, m)))
-    assert still <= (0 if prec == "fp64" else m * m * m // 16384), still
-    ks = sorted({1, 2, 3, m - 3, m - 2, m - 1} |
-                {q + d for q in range(16, m - 3, 16) for d in (-1, 0, 1)})
-    js = [0, 1, 2, 3, 4, 5, m // 2 - 2, m // 2 - 1, m // 2, m // 2 + 1] + list(range(m - 6, m))
-    is_ = [0, 1, 2, 3, m // 2 - 2, m // 2 - 1, m // 2, m // 2 + 1] + list(range(m - 4, m))
+    assert np.array_equal(xn[:, 0], x[:, 0]) and np.array_equal(xn[:, mz], x[:, mz])
+    still = int(sum(np.count_nonzero(xn[:, k] == x[:, k]) for k in range(1, mz)))
+    assert still <= (0 if prec == "fp64" else mx * my * mz // 16384), still
+    ks = sorted({1, 2, 3, mz - 3, mz - 2, mz - 1} |
+                {q + d for q in range(16, mz - 3, 16) for d in (-1, 0, 1)})
+    js = [0, 1, 2, 3, 4, 5, my // 2 - 2, my // 2 - 1, my // 2, my // 2 + 1] + list(range(my - 6, my))
+    is_ = [0, 1, 2, 3, mx // 2 - 2, mx // 2 - 1, mx // 2, mx // 2 + 1] + list(range(mx - 4, mx))
     nodes = list(zip(rng.choice(ks, 2048), rng.choice(js, 2048), rng.choice(is_, 2048)))
-    nodes += list(zip(rng.integers(1, m, 1024), rng.integers(0, m, 1024), rng.integers(0, m, 1024)))
+    nodes += list(zip(rng.integers(1, mz, 1024), rng.integers(0, my, 1024), rng.integers(0, mx, 1024)))
     assert len({(i & 1, j & 1, k & 1) for k, j, i in nodes}) == 8
-    A = fine_stencil(n, 1.0 / n, LAM, MU)
+    A = fine_stencil(nz, 1.0 / nz, LAM, MU)
     if level == 1:
-        A = galerkin_stencil(A, n)
+        A = galerkin_stencil(A, nz)
     want = sweep_at_nodes(A, np.asarray(x, np.float64), np.asarray(xn, np.float64),
                           np.asarray(b, np.float64), nodes, DEFAULT_ORDER)
     got = np.array([xn[:, k, j, i] for k, j, i in nodes], dtype=np.float64)
     err = np.abs(got - want).max() / np.abs(want).max()
-    print("%d^3 level %d %s: sampled sweep error %.3e, unchanged interior values %d"
-          % (n, level, prec, err, still))
+    print("%dx%dx%d level %d %s: sampled sweep error %.3e, unchanged interior values %d"
+          % (nx, ny, nz, level, prec, err, still))
     assert err < (1e-13 if prec == "fp64" else 2e-6), err
 
 
