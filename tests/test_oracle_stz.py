@@ -562,3 +562,29 @@ def test_explicit_method_reaches_the_quasi_static_state():
         assert abs(gaps[-1] - MU * UB * dq) <= 0.05 * MU * UB * dq
     # the explicit stress is uniform too: the waves are gone
     assert np.abs(s[4] - s[4].mean()).max() <= 1e-3 * s[4].mean()
+
+
+@pytest.mark.parametrize("advect", [0, 1])
+def test_stz_step_at_cells_matches_the_whole_grid(advect):
+    """The cell-by-cell evaluation of the oracle's STZ step (which checks the
+    GPU step at full size on sampled cells) equals the oracle's step on the
+    whole grid at every cell of a 12 x 10 x 9 grid, the wall layers and the
+    wrapped first and last rows and columns included, with and without the
+    ENO advection of the stress."""
+    from cell_sample import near_yield_state, stz_step_at_cells
+    rng = np.random.default_rng(23)
+    nx, ny, nz = 12, 10, 9
+    h, dt = 1.0 / nz, 10.0
+    P = stz_constants()
+    v, sig, chi = near_yield_state(rng, nx, ny, nz, P["s_y"])
+    p = dict(P, advect=advect)
+    rs, rc = stz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
+    cells = [(k, j, i) for k in range(nz) for j in range(ny) for i in range(nx)]
+    ss, cn = stz_step_at_cells(v, sig, chi, h, dt, LAM, MU, p, cells)
+    want_s = np.array([rs[:, k, j, i] for k, j, i in cells])
+    want_c = np.array([rc[k, j, i] for k, j, i in cells])
+    assert np.abs(ss - want_s).max() <= 1e-14 * np.abs(want_s).max()
+    assert np.abs(cn - want_c).max() <= 1e-14 * np.abs(want_c - chi.ravel()).max()
+    if advect:
+        r0, _ = stz.stz_step(v, sig, chi, h, dt, LAM, MU, dict(P, advect=0))
+        assert np.abs(rs - r0).max() > 1e-3 * np.abs(rs).max()
