@@ -2,12 +2,13 @@
 and Eq. ENO for the advection) evaluated at single cells of a large grid.
 
 The step at a cell reads the stress and chi of the cells up to two away
-along each axis (the ENO stencils of the advection) and the velocity at its
-own eight corner nodes.  The oracle's step on the 5 x 5 x 5 cells around a
-cell (periodic in x and y, so the patch wraps like the grid) therefore gives
-that cell's result.  Within two cells of a wall the patch is shifted to hold
-the wall layers, so that the ghost layers are extrapolated from the same two
-layers as on the whole grid.  The chi diffusion term (l > 0) is not covered.
+along each axis (the ENO stencils of the advection; the chi diffusion term
+reads D^pl, a function of stress and chi, one cell away) and the velocity at
+its own eight corner nodes.  The oracle's step on the 5 x 5 x 5 cells around
+a cell (periodic in x and y, so the patch wraps like the grid) therefore
+gives that cell's result.  Within two cells of a wall the patch is shifted to
+hold the wall layers, so that the ghost layers are extrapolated from the same
+two layers as on the whole grid.
 
 Test infrastructure: uses only `oracle/`.
 """
@@ -25,8 +26,6 @@ def stz_step_at_cells(v, sigma, chi, h, dt, lam, mu, p, cells):
     [6][nz][ny][nx]; chi: [nz][ny][nx]; p: the oracle's STZ parameters.
     Returns (sigma_star (len(cells), 6), chi_next (len(cells),)).
     """
-    if p.get("l_diff", 0.0) > 0.0:
-        raise ValueError("the chi diffusion term is not evaluated cell by cell")
     nz, ny, nx = chi.shape
     if nz < 5:
         raise ValueError("needs at least 5 cell layers")

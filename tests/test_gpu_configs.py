@@ -187,37 +187,47 @@ def test_sweep_sampled_nodes_full_size(shape, mc, level, prec):
     assert err < (1e-13 if prec == "fp64" else 2e-6), err
 
 
-@pytest.mark.parametrize("advect", [0, 1])
-def test_stz_step_256_sampled_cells(advect):
-    """The STZ step at 256^3 (the launch configuration of the benchmark's step
-    profile), plain and with the ENO advection of the stress (Eq.
-    sig_star_evol, Eq. ENO), on a seeded state around the yield surface:
-    sigma* and chi' at 3072 cells (the wall layers and the two next to them,
-    cells at and next to every multiple of 16, the first, middle and last rows
-    and columns, random cells) equal the oracle's step on the 5 x 5 x 5 cells
-    around each (tests/cell_sample.py): sigma* to 1e-12 of its largest value,
-    the chi increment to 1e-11 of its largest value, as on the small grids."""
+@pytest.mark.parametrize("shape,dt,extra", [
+    ((256, 256, 256), 10.0, {}),
+    ((256, 256, 256), 10.0, {"advect": 1}),
+    ((256, 256, 128), 200.0, {"l_diff": 1.0 / 128, "n_sub": -1}),
+], ids=["256", "256-advect", "defect-256x256x128"])
+def test_stz_step_sampled_cells_full_size(shape, dt, extra):
+    """The STZ step at full size, in the launch configuration the benchmark
+    runs it: at 256^3 plain and with the ENO advection of the stress (Eq.
+    sig_star_evol, Eq. ENO), and on the single-defect run's 256 x 256 x 128
+    grid with its chi diffusion term (l = h) and per-cell plastic sub-steps
+    (dt = 200).  On a seeded state around the yield surface, sigma* and chi'
+    at 3072 cells (the wall layers and the two next to them, cells at and next
+    to every multiple of 16, the first, middle and last rows and columns,
+    random cells) equal the oracle's step on the 5 x 5 x 5 cells around each
+    (tests/cell_sample.py): sigma* to 1e-12 of its largest value, the chi
+    increment to 1e-11 of its largest value, as on the small grids."""
     from cell_sample import near_yield_state, stz_step_at_cells
-    n = 256
-    h, dt = 1.0 / n, 10.0
-    g = solver(n)
-    rng = np.random.default_rng(41 + advect)
-    v, sig, chi = near_yield_state(rng, n, n, n, P["s_y"])
-    p = dict(P, advect=advect)
+    from paper_1904_03808_amd.qsmg import MGSolver
+    nx, ny, nz = shape
+    h = 1.0 / nz
+    g = MGSolver(nx, ny, nz, h, LAM, MU, min_coarse_nz=4)
+    rng = np.random.default_rng(41 + len(extra) + nz)
+    v, sig, chi = near_yield_state(rng, nx, ny, nz, P["s_y"])
+    p = dict(P, **extra)
     ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
-    edge = sorted({0, 1, 2, 3, 4, n // 2 - 1, n // 2, n - 5, n - 4, n - 3, n - 2, n - 1} |
-                  {q + d for q in range(16, n - 4, 16) for d in (-1, 0)})
-    cells = list(zip(rng.choice(edge, 2048), rng.choice(edge, 2048), rng.choice(edge, 2048)))
-    cells += list(zip(rng.integers(0, n, 1024), rng.integers(0, n, 1024), rng.integers(0, n, 1024)))
+
+    def edge(m):
+        return sorted({0, 1, 2, 3, 4, m // 2 - 1, m // 2, m - 5, m - 4, m - 3, m - 2, m - 1} |
+                      {q + d for q in range(16, m - 4, 16) for d in (-1, 0)})
+    cells = list(zip(rng.choice(edge(nz), 2048), rng.choice(edge(ny), 2048), rng.choice(edge(nx), 2048)))
+    cells += list(zip(rng.integers(0, nz, 1024), rng.integers(0, ny, 1024), rng.integers(0, nx, 1024)))
     kk, jj, ii = (torch.as_tensor([c[t] for c in cells], device="cuda") for t in range(3))
     got_s = host(ss[:, kk, jj, ii]).T
     got_c = host(c1[kk, jj, ii])
     del ss, c1
+    g.close()
     want_s, want_c = stz_step_at_cells(v, sig, chi, h, dt, LAM, MU, p, cells)
     chi_s = np.array([chi[k, j, i] for k, j, i in cells])
     es = np.abs(got_s - want_s).max() / np.abs(want_s).max()
     ec = np.abs(got_c - want_c).max() / np.abs(want_c - chi_s).max()
-    print("advect %d: sigma* %.3e, chi increment %.3e" % (advect, es, ec))
+    print("%s: sigma* %.3e, chi increment %.3e" % (extra, es, ec))
     assert es <= 1e-12 and ec <= 1e-11, (es, ec)
 
 

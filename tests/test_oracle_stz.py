@@ -564,13 +564,14 @@ def test_explicit_method_reaches_the_quasi_static_state():
     assert np.abs(s[4] - s[4].mean()).max() <= 1e-3 * s[4].mean()
 
 
-@pytest.mark.parametrize("advect", [0, 1])
-def test_stz_step_at_cells_matches_the_whole_grid(advect):
+@pytest.mark.parametrize("advect,diff", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_stz_step_at_cells_matches_the_whole_grid(advect, diff):
     """The cell-by-cell evaluation of the oracle's STZ step (which checks the
     GPU step at full size on sampled cells) equals the oracle's step on the
     whole grid at every cell of a 12 x 10 x 9 grid, the wall layers and the
     wrapped first and last rows and columns included, with and without the
-    ENO advection of the stress."""
+    ENO advection of the stress, and with and without the chi diffusion term
+    (l = h, per-cell plastic sub-steps)."""
     from cell_sample import near_yield_state, stz_step_at_cells
     rng = np.random.default_rng(23)
     nx, ny, nz = 12, 10, 9
@@ -578,6 +579,8 @@ def test_stz_step_at_cells_matches_the_whole_grid(advect):
     P = stz_constants()
     v, sig, chi = near_yield_state(rng, nx, ny, nz, P["s_y"])
     p = dict(P, advect=advect)
+    if diff:
+        p.update(l_diff=h, n_sub=-1)
     rs, rc = stz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
     cells = [(k, j, i) for k in range(nz) for j in range(ny) for i in range(nx)]
     ss, cn = stz_step_at_cells(v, sig, chi, h, dt, LAM, MU, p, cells)
@@ -586,5 +589,8 @@ def test_stz_step_at_cells_matches_the_whole_grid(advect):
     assert np.abs(ss - want_s).max() <= 1e-14 * np.abs(want_s).max()
     assert np.abs(cn - want_c).max() <= 1e-14 * np.abs(want_c - chi.ravel()).max()
     if advect:
-        r0, _ = stz.stz_step(v, sig, chi, h, dt, LAM, MU, dict(P, advect=0))
+        r0, _ = stz.stz_step(v, sig, chi, h, dt, LAM, MU, dict(p, advect=0))
         assert np.abs(rs - r0).max() > 1e-3 * np.abs(rs).max()
+    if diff:
+        _, c0 = stz.stz_step(v, sig, chi, h, dt, LAM, MU, dict(p, l_diff=0.0))
+        assert np.abs(rc - c0).max() > 1e-3 * np.abs(rc - chi).max()
