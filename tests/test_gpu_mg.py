@@ -239,6 +239,56 @@ def test_row_sweep_matches_oracle(n, mc, prec):
             assert rel(host(xd).astype(np.float64), xr) < tol, (level, sweeps)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
+def test_rows_beyond_the_row_sweep(prec):
+    """Rows of 1024 nodes (1024 x 16 x 16, coarsened to 128 x 2 x 2): too
+    long for the fine row sweep's LDS ring, so the fine level is smoothed one
+    colour per launch; its 512-wide level 1 is the widest row the two-colour
+    launch takes (one row of 256 column pairs per workgroup, the neighbour
+    pairs' new values through LDS), and 256 x 4 x 4 below it.  One and three
+    sweeps on every smoothed level match the oracle's; the first two FP64
+    V-cycles match it element by element, and the FP32-IR solve reaches a
+    relative residual of 1e-10 by the oracle's operator (the domain is 64
+    units long in x, so its condition number is large and the residual, not
+    the distance to another solution, is the bar)."""
+    rng = np.random.default_rng(17)
+    n = (1024, 16, 16)
+    g, o = make(*n, precision=prec, min_coarse_nz=2)
+    assert g.levels == len(o.levels) == 4
+    assert [g.level_dims(lv) for lv in range(4)] == [(1024, 16, 16), (512, 8, 8), (256, 4, 4),
+                                                     (128, 2, 2)]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    tol = 1e-13 if prec == "fp64" else 2e-6
+    for level in range(3):
+        L = o.levels[level]
+        x = rand_node(rng, L.nx, L.ny, L.nz, walls=(level == 0))
+        b = rand_node(rng, L.nx, L.ny, L.nz)
+        for sweeps in (1, 3):
+            xd = torch.from_numpy(x).to("cuda", dt)
+            g.smooth(level, xd, torch.from_numpy(b).to("cuda", dt), sweeps)
+            xr = x.astype(np.float32).astype(np.float64) if prec != "fp64" else x.copy()
+            br = b.astype(np.float32).astype(np.float64) if prec != "fp64" else b
+            for _ in range(sweeps):
+                L.sweep(xr, br, o.order)
+            assert rel(host(xd).astype(np.float64), xr) < tol, (level, sweeps)
+    b = rand_node(rng, *n)
+    x0 = rand_node(rng, *n)
+    if prec == "fp64":
+        for k in (1, 2):
+            xd = dev(x0)
+            g.solve(dev(b), xd, rtol=0.0, max_cycles=k)
+            x_ref, _ = o.solve(b, x0, rtol=0.0, max_cycles=k)
+            assert rel(host(xd), x_ref) < 1e-12, k
+    else:
+        xd = dev(x0)
+        info = g.solve(dev(b), xd, rtol=1e-10)
+        assert info.converged
+        x = host(xd)
+        assert np.array_equal(x[:, 0], x0[:, 0]) and np.array_equal(x[:, -1], x0[:, -1])
+        res = np.linalg.norm(o.residual(x, b)[:, 1:-1]) / o.lifted_rhs_norm(b, x0)
+        assert res <= 1.2e-10, res
+
+
 def test_colour_passes_128_wide_level():
     """256 x 256 x 32 on five levels (coarsest 16 x 16 x 2): level 1 is
     128 x 128 x 16, the row width of the 128^3 level, smoothed by the
