@@ -403,6 +403,33 @@ def test_single_level_direct():
     assert rel(host(xd), xr) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
+@pytest.mark.parametrize("n", [(7, 5, 6), (5, 9, 3)])
+def test_single_level_odd_shapes(n, prec):
+    """Odd dimensions are allowed on a grid that is not coarsened (nz <=
+    min_coarse_nz): the operator matches the oracle's, and the solve (the
+    dense inverse, with Dirichlet data on the walls) reaches the oracle's
+    direct solution: 1e-12 in FP64, 1e-8 in FP32-IR after its refinement to
+    a relative residual of 1e-12."""
+    rng = np.random.default_rng(19)
+    g, _ = make(*n, precision=prec)
+    assert g.levels == 1
+    h = 1.0 / n[2]
+    x = rand_node(rng, *n)
+    if prec == "fp64":
+        assert rel(host(g.apply(dev(x))), apply_elastic(x, h, LAM, MU)) < 1e-13
+    b = rand_node(rng, *n)
+    x0 = np.zeros_like(b)
+    x0[:, 0] = rng.standard_normal(x0[:, 0].shape)
+    x0[:, -1] = rng.standard_normal(x0[:, -1].shape)
+    xd = dev(x0)
+    info = g.solve(dev(b), xd, rtol=1e-12)
+    assert info.converged
+    xr = direct_solve(b, x0, h, LAM, MU)
+    assert rel(host(xd), xr) < (1e-12 if prec == "fp64" else 1e-8)
+    assert np.array_equal(host(xd)[:, 0], x0[:, 0]) and np.array_equal(host(xd)[:, -1], x0[:, -1])
+
+
 def test_calls_under_another_stream_are_refused():
     """The handle is bound to the stream current at construction: a call made
     while another torch stream is current raises instead of running unordered
