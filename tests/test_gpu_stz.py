@@ -198,6 +198,40 @@ def test_rhs_and_stress_update(n):
     assert rel(out, ostz.stress_update(s, v, 1.0 / nz, 0.3, LAM, MU)) < 1e-13
 
 
+@pytest.mark.parametrize("n", [(7, 5, 6), (9, 7, 3)])
+def test_odd_shapes(n):
+    """Odd cell counts (a single multigrid level, where odd sizes are allowed;
+    the 16 x 16 cell tiles of the advecting step are ragged in x and y and
+    the ENO stencils wrap around fewer than 16 cells): the STZ step, plain,
+    with the advection, with the chi diffusion and per-cell sub-steps, and
+    with backward Euler, matches the oracle (sigma* 1e-12, the chi increment
+    1e-11), and so do two projection steps (v and sigma 1e-10, chi 1e-13)."""
+    rng = np.random.default_rng(27)
+    nx, ny, nz = n
+    h, dt = 1.0 / nz, 10.0
+    g = solver(nx, ny, nz)
+    assert g.levels == 1
+    v, sig, chi = random_state(rng, nx, ny, nz)
+    for extra in ({}, {"advect": 1}, {"l_diff": h, "n_sub": -1}, {"n_sub": -2}):
+        p = dict(P, **extra)
+        ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
+        rs, rc = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
+        assert rel(host(ss), rs) < 1e-12, extra
+        assert rel(host(c1) - chi, rc - chi) < 1e-11, extra
+    # from the random state (a uniform shear state would already be in
+    # equilibrium, with nothing for the solve to do)
+    U = 1e-5
+    o = MGOracle(nx, ny, nz, h, LAM, MU)
+    vd, sd, cd = dev(v), dev(sig), dev(chi)
+    for step in range(2):
+        info = g.projection_step(P, dt, U, vd, sd, cd, rtol=1e-12)
+        v, sig, chi, _ = ostz.projection_step(v, sig, chi, h, dt, LAM, MU, P, U, o, rtol=1e-12)
+        assert info.converged and info.cycles >= 1
+        assert rel(host(vd), v) < 1e-10, step
+        assert rel(host(sd), sig) < 1e-10, step
+        assert rel(host(cd), chi) < 1e-13, step
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
 def test_projection_steps(prec):
     """Three simple-shear steps at 16^3 from a random chi field."""
