@@ -618,16 +618,16 @@ def table3_shapes(Ns=(128, 256, 384, 512, 768), reps: int = 3) -> dict:
     return out
 
 
-def profile_solve(n: int) -> None:
-    """Kernels for hardware-counter runs of a whole V-cycle: two FP32-IR cycles
-    (fixed count, no convergence test) of the n^3 bench system."""
+def profile_solve(n: int, precision: str = "fp32-ir") -> None:
+    """Kernels for hardware-counter runs of a whole V-cycle: two cycles (fixed
+    count, no convergence test) of the n^3 bench system, FP32-IR or FP64."""
     import torch
 
     from paper_1904_03808_amd.qsmg import MGSolver
     from workloads import lame, stress_field
     lam, mu = lame()
     dev = torch.device("cuda:0")
-    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision="fp32-ir", device=dev)
+    g = MGSolver(n, n, n, 1.0 / n, lam, mu, precision=precision, device=dev)
     sig_host = stress_field(n, n, n, 2)
     sig = torch.from_numpy(sig_host).to(dev)
     b = g.rhs(sig, 1.0)
@@ -635,7 +635,7 @@ def profile_solve(n: int) -> None:
     x = torch.zeros_like(b)
     g.solve(b, x, rtol=0.0, max_cycles=2, raise_on_failure=False)
     torch.cuda.synchronize()
-    print(json.dumps({"profiled": "fp32-ir solve", "cycles": 2}), flush=True)
+    print(json.dumps({"profiled": precision + " solve", "cycles": 2}), flush=True)
 
 
 def profile_step(n: int) -> None:
@@ -727,6 +727,8 @@ def main():
                     help="only time V-cycles on the paper's N x N x N/2 grids and print them")
     ap.add_argument("--profile-solve", action="store_true",
                     help="only run two FP32-IR V-cycles (for rocprofv3 counters)")
+    ap.add_argument("--profile-solve-fp64", action="store_true",
+                    help="only run two FP64 V-cycles (for rocprofv3 counters)")
     ap.add_argument("--profile-smoother", action="store_true",
                     help="only run a calibration copy and fine-level sweeps (for rocprofv3 counters)")
     ap.add_argument("--profile-step", action="store_true",
@@ -746,8 +748,8 @@ def main():
     if args.profile_smoother:
         profile_smoother(args.n)
         return
-    if args.profile_solve:
-        profile_solve(args.n)
+    if args.profile_solve or args.profile_solve_fp64:
+        profile_solve(args.n, "fp64" if args.profile_solve_fp64 else "fp32-ir")
         return
     if args.profile_step:
         profile_step(args.n)

@@ -20,5 +20,6 @@ def test_help_lists_the_blocks():
     assert r.returncode == 0
     for opt in ("--steps", "--warmup", "--no-512", "--no-steps", "--no-defect", "--no-table3",
                 "--paper-run", "--explicit-only", "--table3-only", "--defect-only",
-                "--profile-smoother", "--profile-solve", "--profile-step", "--chi-wall", "--min-coarse-nz"):
+                "--profile-smoother", "--profile-solve", "--profile-solve-fp64", "--profile-step",
+                "--chi-wall", "--min-coarse-nz"):
         assert opt in r.stdout, opt
