@@ -89,6 +89,20 @@ def test_level_planning_on_the_host(lib):
     p = params(40, 24, 32)
     assert lib.qs_level_dims(C.byref(p), 2, C.byref(n), *[C.byref(d) for d in dims]) == _capi.QS_OK
     assert n.value == 3 and [d.value for d in dims] == [10, 6, 8]
+    # 1024-wide rows down to 128 x 2 x 2
+    p = params(1024, 16, 16, min_coarse_nz=2)
+    got = []
+    for lv in range(4):
+        assert lib.qs_level_dims(C.byref(p), lv, C.byref(n), *[C.byref(d) for d in dims]) == _capi.QS_OK
+        got.append([d.value for d in dims])
+    assert n.value == 4 and got == [[1024, 16, 16], [512, 8, 8], [256, 4, 4], [128, 2, 2]]
+    # odd sizes: allowed on a level that is not coarsened, refused where one must be
+    p = params(7, 5, 6)
+    assert lib.qs_level_dims(C.byref(p), 0, C.byref(n), *[C.byref(d) for d in dims]) == _capi.QS_OK
+    assert n.value == 1 and [d.value for d in dims] == [7, 5, 6]
+    for shape in ((7, 6, 10), (8, 6, 18)):  # odd on the fine level; odd nz = 9 on level 1
+        p = params(*shape)
+        assert lib.qs_level_dims(C.byref(p), 0, C.byref(n), None, None, None) == _capi.QS_ERR_SHAPE, shape
 
 
 def test_workspace_sizing_and_argument_errors(lib):
