@@ -404,13 +404,15 @@ def test_single_level_direct():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
-@pytest.mark.parametrize("n", [(7, 5, 6), (5, 9, 3)])
+@pytest.mark.parametrize("n", [(7, 5, 6), (5, 9, 3), (2, 2, 2), (2, 3, 4), (3, 2, 2)])
 def test_single_level_odd_shapes(n, prec):
     """Odd dimensions are allowed on a grid that is not coarsened (nz <=
-    min_coarse_nz): the operator matches the oracle's, and the solve (the
-    dense inverse, with Dirichlet data on the walls) reaches the oracle's
-    direct solution: 1e-12 in FP64, 1e-8 in FP32-IR after its refinement to
-    a relative residual of 1e-12."""
+    min_coarse_nz), and so are the degenerate periodic lengths of 2, where a
+    node's two neighbours along x (or y) are one node and their couplings add
+    up (one interior plane at nz = 2): the operator matches the oracle's, and
+    the solve (the dense inverse, with Dirichlet data on the walls) reaches
+    the oracle's direct solution: 1e-12 in FP64, 1e-8 in FP32-IR after its
+    refinement to a relative residual of 1e-12."""
     rng = np.random.default_rng(19)
     g, _ = make(*n, precision=prec)
     assert g.levels == 1
