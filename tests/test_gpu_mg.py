@@ -387,6 +387,31 @@ def test_edge_cases():
     assert torch.count_nonzero(flat).item() == 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32-ir"])
+def test_zero_cycles_and_a_converged_start(prec):
+    """max_cycles = 0 runs no cycle: x is left as it was, bit for bit, the
+    status says not converged, and the relative residual reported is the
+    oracle's for the start; a start that already meets rtol (the oracle's
+    direct solution) returns after no cycle with status OK and x unchanged."""
+    from paper_1904_03808_amd._capi import QS_ERR_NOT_CONVERGED, QS_OK
+    rng = np.random.default_rng(23)
+    n = (16, 16, 16)
+    g, o = make(*n, precision=prec)
+    b = rand_node(rng, *n)
+    x0 = rand_node(rng, *n)
+    xd = dev(x0)
+    info = g.solve(dev(b), xd, rtol=1e-10, max_cycles=0, raise_on_failure=False)
+    assert info.status == QS_ERR_NOT_CONVERGED and info.cycles == 0
+    assert np.array_equal(host(xd), x0)
+    rel0 = np.linalg.norm(o.residual(x0, b)[:, 1:-1]) / o.lifted_rhs_norm(b, x0)
+    assert abs(info.rel_res - rel0) <= 1e-12 * rel0, (info.rel_res, rel0)
+    xs = direct_solve(b, x0, 1.0 / n[2], LAM, MU)
+    xd = dev(xs)
+    info = g.solve(dev(b), xd, rtol=1e-10, max_cycles=10, raise_on_failure=False)
+    assert info.status == QS_OK and info.cycles == 0 and info.rel_res <= 1e-10
+    assert np.array_equal(host(xd), xs)
+
+
 def test_single_level_direct():
     """nz <= min_coarse_nz: one level solved by the dense inverse, walls lifted."""
     rng = np.random.default_rng(9)
