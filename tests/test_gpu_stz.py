@@ -198,6 +198,44 @@ def test_rhs_and_stress_update(n):
     assert rel(out, ostz.stress_update(s, v, 1.0 / nz, 0.3, LAM, MU)) < 1e-13
 
 
+def test_deviator_free_stress_and_a_start_from_rest():
+    """Stress without a deviator (sbar = 0: zero stress, the paper's start,
+    and a pure pressure) is below yield everywhere: the STZ step in all its
+    forms leaves chi exactly as it was and matches the oracle's sigma* (the
+    elastic increment and, under pressure, the kinematic terms); two
+    projection steps from rest (sigma = 0, v = 0 inside, the shear walls
+    moving) match the oracle's (v and sigma 1e-10, chi exactly)."""
+    rng = np.random.default_rng(29)
+    nx, ny, nz = 16, 12, 8
+    h, dt, U = 1.0 / nz, 10.0, 1e-5
+    g = solver(nx, ny, nz)
+    v = 1e-4 * rng.standard_normal((3, nz + 1, ny, nx)) + shear_velocity(nx, ny, nz, U)
+    chi = 0.05 + 0.003 * rng.standard_normal((nz, ny, nx))
+    zero = np.zeros((6, nz, ny, nx))
+    pressure = zero.copy()
+    pressure[:3] = -0.01
+    for sig in (zero, pressure):
+        for extra in ({}, {"advect": 1}, {"l_diff": h, "n_sub": -1}, {"n_sub": -2}):
+            p = dict(P, **extra)
+            ss, c1 = g.stz_step(p, dt, dev(v), dev(sig), dev(chi))
+            rs, rc = ostz.stz_step(v, sig, chi, h, dt, LAM, MU, p)
+            assert np.array_equal(rc, chi) and np.array_equal(host(c1), chi), extra
+            assert rel(host(ss), rs) < 1e-12, extra
+    o = MGOracle(nx, ny, nz, h, LAM, MU, min_coarse_nz=2)
+    g2 = solver(nx, ny, nz, min_coarse_nz=2)
+    v0 = np.zeros((3, nz + 1, ny, nx))
+    v0[0, 0], v0[0, -1] = -U, U
+    vr, sr, cr = v0, zero, chi
+    vd, sd, cd = dev(v0), dev(zero), dev(chi)
+    for step in range(2):
+        info = g2.projection_step(P, dt, U, vd, sd, cd, rtol=1e-12)
+        vr, sr, cr, _ = ostz.projection_step(vr, sr, cr, h, dt, LAM, MU, P, U, o, rtol=1e-12)
+        assert info.converged
+        assert rel(host(vd), vr) < 1e-10, step
+        assert rel(host(sd), sr) < 1e-10, step
+        assert np.array_equal(host(cd), cr), step
+
+
 @pytest.mark.parametrize("n", [(7, 5, 6), (9, 7, 3)])
 def test_odd_shapes(n):
     """Odd cell counts (a single multigrid level, where odd sizes are allowed;
