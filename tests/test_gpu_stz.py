@@ -390,14 +390,16 @@ def test_projection_step_walls_rejects_bad_wall_arrays():
 
 
 @pytest.mark.parametrize("n,extra", [((16, 16, 16), {}), ((24, 20, 12), {"n_sub": -1}),
-                                     ((12, 10, 2), {})])
+                                     ((12, 10, 2), {}), ((64, 64, 32), {})])
 def test_explicit_steps(n, extra):
     """Five steps of the explicit method (Sec. 3.2: node velocity with
     divergence of stress, ENO advection and damping kappa = 4.8 h, stress
     with advection, chi) at dt = h^2/20 under simple shear, from a state with
     stresses around yield, match the oracle's; nz = 2 puts both walls' ghost
-    nodes into every z stencil.  (chi diffusion is left out here: on these
-    rough random states it drives chi, and then cosh, past overflow.)"""
+    nodes into every z stencil, and 64 x 64 x 32 is the grid on which the
+    benchmark times the method against the quasi-static one.  (chi diffusion
+    is left out here: on these rough random states it drives chi, and then
+    cosh, past overflow.)"""
     rng = np.random.default_rng(8)
     nx, ny, nz = n
     h = 1.0 / nz
