@@ -403,7 +403,7 @@ def test_explicit_steps(n, extra):
     rng = np.random.default_rng(8)
     nx, ny, nz = n
     h = 1.0 / nz
-    g = solver(nx, ny, nz)
+    g = solver(nx, ny, nz, min_coarse_nz=4)  # the benchmark's hierarchy on 64 x 64 x 32
     v, sig, chi = random_state(rng, nx, ny, nz)
     U, dt, rho, kappa = 1e-3, h * h / 20, MU, 4.8 * h
     v = v + shear_velocity(nx, ny, nz, U)
