@@ -67,9 +67,10 @@ typedef enum {
 typedef enum { QS_FP64 = 0, QS_FP32_IR = 1 } qs_precision;
 
 /* Multigrid parameters (Sec. 3.6).  Coarsening halves every dimension while
- * nz > min_coarse_nz; each coarsened level needs even nx, ny, nz and at least
- * 4 cells per dimension; the coarsest level is solved with a dense FP64
- * inverse (at most QS_MAX_COARSE unknowns).  Kernels index arrays with 32-bit
+ * nz > min_coarse_nz (at least 2); each coarsened level needs even nx, ny, nz
+ * and at least 4 cells per dimension, while the coarsest level (the only one
+ * when nz <= min_coarse_nz) may have odd sizes down to 2 cells per dimension;
+ * it is solved with a dense FP64 inverse (at most QS_MAX_COARSE unknowns).  Kernels index arrays with 32-bit
  * integers, so 3 (nz+1) ny nx (node vector) and 6 nz ny nx (cell tensor)
  * must stay below 2^31 (512^3 passes, 640 x 640 x 1024 does not); larger
  * grids are refused with QS_ERR_SHAPE.  colour_order lists the 8 node
